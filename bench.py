@@ -1,0 +1,194 @@
+"""Throughput of the fused central-moment stream-and-collide step on one GPU.
+
+Workload: coupled D2Q9 flow (f) + heat (h) lattices on a 2048 x 2048 grid in
+FP32 storage, two-array (AB) streaming: heated cylinder of radius 64 (IBB for
+f, IABB for h), equilibrium inlet column with a seeded perturbation of the
+inlet velocity, zero-gradient outlet column, periodic in y; Re = 100 (u = 0.04,
+D = 128, nu = 0.0512), Pr = 0.71.  Synthetic inputs, all resident in HBM before
+the timed region.
+
+Prints one JSON line: MLUPS (nodes x steps / s / 1e6) of the whole job, the HBM
+roofline of the dominant (bulk) kernel from HIP events recorded around every
+launch in the timed region, and the FP64 CPU oracle timed on a bounded sample
+of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12  # MI355X HBM3E, B/s
+METRIC = "MLUPS + % HBM roofline (fwd CM stream-collide); adjoint/forward step-time ratio"
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2203_01316_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload: str):
+    """HBM bytes per bulk launch from the committed rocprofv3 counter summary,
+    or None if there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_digest") != source_digest():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_ceiling(torch, dev, nbytes=2 << 30, reps=20):
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    return 2 * nbytes / sec
+
+
+def cpu_baseline(inputs, steps):
+    from oracle import oracle as O
+
+    flags, q, groups, u, rho0, H0, nx, ny, nu, k = inputs
+    sf = O.preset(9, "ns", O.s_main(nu))
+    sh = O.preset(9, "trt", O.s_main(k))
+    o = O.Sim(9, nx, ny, with_ns=True, s_f=sf, s_h=sh, uvel=u, flags=flags, qlink=q, groups=groups)
+    o.init(H0, u=u, rho=rho0)
+    t0 = time.perf_counter()
+    o.step(steps)
+    sec = time.perf_counter() - t0
+    return {"value": nx * ny * steps / sec / 1e6, "unit": "MLUPS", "cores": int(O.lib().ora_threads()),
+            "kind": "oracle",
+            "sample": f"{steps} steps of the same {nx}x{ny} coupled workload, FP64 oracle "
+                      f"({sec:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--nx", type=int, default=2048)
+    ap.add_argument("--ny", type=int, default=2048)
+    ap.add_argument("--storage", default="fp32")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: only one GPU is supported in this build (got --gpus {args.gpus}); the kernel "
+              "shards by slabs, but no multi-GPU path is built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2203_01316_amd import lbm as L
+    from paper_2203_01316_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    nx, ny = args.nx, args.ny
+    nu = 0.04 * 128 / 100.0
+    k = nu / 0.71
+    flags, q, groups, u, rho0, H0 = W.heated_cylinder(nx, ny, 64, u_in=0.04, amp=1e-3, seed=0)
+    uf = np.asarray(u, np.float32)
+    g = L.LBM(L.D2Q9, nx, ny, with_ns=True, storage=args.storage, nu=nu, k=k, relax_f="ns", relax_h="trt",
+              flags=flags, q=q, groups=groups, device=dev)
+    g.set_velocity(uf)
+    g.init(H0, u=uf.astype(np.float64), rho=rho0)
+    n = nx * ny
+    nl, nspecial = L.count_geometry(g.params, flags)
+    nsolid = int(np.count_nonzero((flags & 15) == L.SOLID))
+    n_bulk = n - nspecial - nsolid
+
+    ceiling = copy_ceiling(torch, dev)
+
+    g.step(args.warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    g.profile_begin(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    g.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    bulk_ms, boundary_ms, timed = g.profile_end()
+    gpu_sec = e0.elapsed_time(e1) / 1e3
+    sec = max(wall, gpu_sec)
+    red = g.reduce(group=1, columns=[50, nx - 101])
+
+    bytes_node = 2 * 2 * 9 * (8 if args.storage == "fp64" else 4 if args.storage.startswith("fp32") else 2)
+    mlups = n * args.steps / sec / 1e6
+    bulk_avg = bulk_ms / 1e3 / max(timed, 1)
+    achieved = n_bulk * bytes_node / bulk_avg
+    traffic = read_traffic(f"d2q9_ns_ade_{nx}x{ny}_{args.storage}")
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.storage != "fp64" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"d2q9_ns_ade_heated_cylinder_{nx}x{ny}", "lattice": "D2Q9",
+                   "lattices": "f (NS, CM) + h (ADE, CM-TRT)", "nx": nx, "ny": ny,
+                   "storage": args.storage, "stream": "AB", "Re": 100, "Pr": 0.71,
+                   "bytes_per_node": bytes_node, "boundary_nodes": nspecial, "solid_nodes": nsolid},
+        "pct_hbm_roofline": round(100.0 * mlups * 1e6 * bytes_node / HBM_PEAK, 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved / 1e9, 1), "peak": HBM_PEAK / 1e9,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
+                     "traffic": None if traffic is None else int(traffic),
+                     "kernel": "k_bulk", "avg_launch_us": round(bulk_avg * 1e6, 2),
+                     "bytes_per_launch": n_bulk * bytes_node},
+        "boundary_kernel_avg_us": round(boundary_ms / 1e3 / max(timed, 1) * 1e6, 2),
+        "copy_ceiling_GBps": round(ceiling / 1e9, 1),
+        "mass": red[0],
+        "energy": red[1],
+    }
+    if not args.no_cpu:
+        inputs = (flags, q, groups, uf.astype(np.float64), rho0, H0, nx, ny, nu, k)
+        out["cpu_baseline"] = cpu_baseline(inputs, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -36,8 +36,20 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORA_MAXQ 27
+
+/* Threads the node loops may use (1 without OpenMP). */
+int ora_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* ---------------------------------------------------------------------------
  * Velocity sets and moment orders.
@@ -610,22 +622,38 @@ int ora_init_post(const ora_cfg *c, const double *rho, const double *u, const do
                   double *fs, double *hs) {
   ora_ctx C;
   long N;
+  double *feq, *heq;
   if (check_cfg(c) || ctx_init(c->Q, &C)) return -1;
   N = nnodes(c);
-  for (long n = 0; n < N; n++) {
+  feq = (double *)malloc(sizeof(double) * c->Q * N);
+  heq = (double *)malloc(sizeof(double) * c->Q * N);
+  if (!feq || !heq) {
+    free(feq);
+    free(heq);
+    return -1;
+  }
+  /* equilibrium of every node from its own fields */
+#pragma omp parallel for schedule(static)
+  for (long m = 0; m < N; m++) {
+    double um[3], geq[ORA_MAXQ];
+    for (int d = 0; d < 3; d++) um[d] = u[d * N + m];
+    if (c->Q == 9) um[2] = 0.0;
+    if (c->with_ns) {
+      equilibrium(&C, rho[m], um, geq);
+      for (int a = 0; a < c->Q; a++) feq[a * N + m] = geq[a];
+    }
+    equilibrium(&C, H[m], um, geq);
+    for (int a = 0; a < c->Q; a++) heq[a * N + m] = geq[a];
+  }
+  /* g*_a(x) = g^eq_a(x + e_a) */
+  for (long n = 0; n < N; n++)
     for (int a = 0; a < c->Q; a++) {
       long m = neighbour(c, n, C.L.e[a], +1);
-      double um[3], geq[ORA_MAXQ];
-      for (int d = 0; d < 3; d++) um[d] = u[d * N + m];
-      if (c->Q == 9) um[2] = 0.0;
-      if (c->with_ns) {
-        equilibrium(&C, rho[m], um, geq);
-        fs[a * N + n] = geq[a];
-      }
-      equilibrium(&C, H[m], um, geq);
-      hs[a * N + n] = geq[a];
+      if (c->with_ns) fs[a * N + n] = feq[a * N + m];
+      hs[a * N + n] = heq[a * N + m];
     }
-  }
+  free(feq);
+  free(heq);
   return 0;
 }
 

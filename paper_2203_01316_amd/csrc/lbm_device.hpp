@@ -1,0 +1,249 @@
+// lbm_device.hpp -- device-side building blocks of the fused central-moment
+// lattice Boltzmann step for gfx950: lattice tables, storage conversion, the
+// factorised raw/central-moment transforms, relaxation and the wall rules.
+//
+// Populations live in registers in "chimera" slots: the population of
+// velocity (ex, ey, ez) sits in slot (ex+1)*9 + (ey+1)*3 + (ez+1) (D3Q27) or
+// (ex+1)*3 + (ey+1) (D2Q9).  Because every velocity component is in
+// {-1, 0, 1} and every moment index in {0, 1, 2}, the central-moment transform
+// T(u) = N(u) M of Sec. 2.1 / App. C is a tensor product of one 3x3 transform
+// per axis; applying it axis by axis (z, then y, then x) turns the slot of
+// velocity (ex, ey, ez) into the slot of central moment (m, n, o).  Relaxation
+// then acts per slot, and the inverse per-axis transform (x, y, z) gives the
+// post-collision populations.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// Lattices.  Direction order: D3Q27 as in Sec. 2.1; D2Q9 is its e_z = 0
+// subset in the same order.
+// ---------------------------------------------------------------------------
+template <int Q>
+struct Lat;
+
+template <>
+struct Lat<9> {
+  static constexpr int D = 2;
+  __host__ __device__ static constexpr int ex(int i) {
+    constexpr int t[9] = {0, 1, 0, 1, -1, 0, 1, -1, -1};
+    return t[i];
+  }
+  __host__ __device__ static constexpr int ey(int i) {
+    constexpr int t[9] = {0, 0, 1, 1, 0, -1, -1, 1, -1};
+    return t[i];
+  }
+  __host__ __device__ static constexpr int ez(int) { return 0; }
+  __host__ __device__ static constexpr int opp(int i) {
+    constexpr int t[9] = {0, 4, 5, 8, 1, 2, 7, 6, 3};
+    return t[i];
+  }
+  // chimera slot of direction i
+  __host__ __device__ static constexpr int slot(int i) { return (ex(i) + 1) * 3 + (ey(i) + 1); }
+};
+
+template <>
+struct Lat<27> {
+  static constexpr int D = 3;
+  __host__ __device__ static constexpr int ex(int i) {
+    constexpr int t[27] = {0, 1, 0, 0, 1, 1, 0, -1, 0, 0, 1, 1, -1, -1,
+                           0, 0, 1, -1, -1, 0, -1, 1, 1, 1, -1, -1, -1};
+    return t[i];
+  }
+  __host__ __device__ static constexpr int ey(int i) {
+    constexpr int t[27] = {0, 0, 1, 0, 1, 0, 1, 0, -1, 0, -1, 0, 1, 0,
+                           1, -1, 1, -1, 0, -1, 1, -1, 1, -1, 1, -1, -1};
+    return t[i];
+  }
+  __host__ __device__ static constexpr int ez(int i) {
+    constexpr int t[27] = {0, 0, 0, 1, 0, 1, 1, 0, 0, -1, 0, -1, 0, 1,
+                           -1, 1, 1, 0, -1, -1, 1, 1, -1, -1, -1, 1, -1};
+    return t[i];
+  }
+  __host__ __device__ static constexpr int opp(int i) {
+    constexpr int t[27] = {0, 7, 8, 9, 17, 18, 19, 1, 2, 3, 12, 13, 10, 11,
+                           15, 14, 26, 4, 5, 6, 23, 24, 25, 20, 21, 22, 16};
+    return t[i];
+  }
+  __host__ __device__ static constexpr int slot(int i) {
+    return (ex(i) + 1) * 9 + (ey(i) + 1) * 3 + (ez(i) + 1);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Storage <-> arithmetic conversion.  DEV storages keep g_i - w_i g_ref.
+// ---------------------------------------------------------------------------
+template <class S>
+struct StoreT;
+template <>
+struct StoreT<double> {
+  __device__ static double ld(const double *p) { return __builtin_nontemporal_load(p); }
+  __device__ static void st(double *p, double v) { __builtin_nontemporal_store(v, p); }
+};
+template <>
+struct StoreT<float> {
+  __device__ static float ld(const float *p) { return __builtin_nontemporal_load(p); }
+  __device__ static void st(float *p, float v) { __builtin_nontemporal_store(v, p); }
+};
+template <>
+struct StoreT<__half> {
+  __device__ static float ld(const __half *p) {
+    unsigned short b = __builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p));
+    return __half2float(__ushort_as_half(b));
+  }
+  __device__ static void st(__half *p, float v) {
+    unsigned short b = __half_as_ushort(__float2half_rn(v));
+    __builtin_nontemporal_store(b, reinterpret_cast<unsigned short *>(p));
+  }
+};
+
+// Rest-equilibrium weight of direction i (product of 1-D weights 2/3, 1/6).
+template <int Q, class R>
+__host__ __device__ constexpr R weight(int i) {
+  R w = R(1);
+  int c[3] = {Lat<Q>::ex(i), Lat<Q>::ey(i), Lat<Q>::ez(i)};
+  for (int d = 0; d < Lat<Q>::D; d++) w *= (c[d] == 0) ? R(2) / R(3) : R(1) / R(6);
+  return w;
+}
+
+// ---------------------------------------------------------------------------
+// One-axis central-moment transform of three populations at velocities
+// -1, 0, +1 (a, b, c) about velocity u:
+//   k0 = a + b + c,  k1 = sum (e - u) g,  k2 = sum (e - u)^2 g.
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ void fwd3(R &a, R &b, R &c, R u) {
+  const R k0 = a + b + c;
+  const R d = c - a;
+  const R k1 = d - u * k0;
+  const R k2 = (c + a) - R(2) * u * d + u * u * k0;
+  a = k0;
+  b = k1;
+  c = k2;
+}
+
+// Inverse of fwd3: (K0, K1, K2) -> populations at -1, 0, +1.
+template <class R>
+__device__ __forceinline__ void inv3(R &a, R &b, R &c, R u) {
+  const R K0 = a, K1 = b, K2 = c;
+  const R D = K1 + u * K0;                    // c - a
+  const R S = K2 + R(2) * u * K1 + u * u * K0; // c + a
+  a = R(0.5) * (S - D);
+  b = K0 - S;
+  c = R(0.5) * (S + D);
+}
+
+// In-place transform of the chimera slots to central moments (slot m,n[,o]).
+template <int D, class R>
+__device__ __forceinline__ void to_central(R *g, R ux, R uy, R uz) {
+  if constexpr (D == 2) {
+#pragma unroll
+    for (int cx = 0; cx < 3; cx++) fwd3(g[cx * 3 + 0], g[cx * 3 + 1], g[cx * 3 + 2], uy);
+#pragma unroll
+    for (int my = 0; my < 3; my++) fwd3(g[0 + my], g[3 + my], g[6 + my], ux);
+  } else {
+#pragma unroll
+    for (int cxy = 0; cxy < 9; cxy++) fwd3(g[cxy * 3 + 0], g[cxy * 3 + 1], g[cxy * 3 + 2], uz);
+#pragma unroll
+    for (int cx = 0; cx < 3; cx++)
+#pragma unroll
+      for (int mz = 0; mz < 3; mz++)
+        fwd3(g[cx * 9 + 0 + mz], g[cx * 9 + 3 + mz], g[cx * 9 + 6 + mz], uy);
+#pragma unroll
+    for (int myz = 0; myz < 9; myz++) fwd3(g[myz], g[9 + myz], g[18 + myz], ux);
+  }
+}
+
+template <int D, class R>
+__device__ __forceinline__ void from_central(R *g, R ux, R uy, R uz) {
+  if constexpr (D == 2) {
+#pragma unroll
+    for (int my = 0; my < 3; my++) inv3(g[0 + my], g[3 + my], g[6 + my], ux);
+#pragma unroll
+    for (int cx = 0; cx < 3; cx++) inv3(g[cx * 3 + 0], g[cx * 3 + 1], g[cx * 3 + 2], uy);
+  } else {
+#pragma unroll
+    for (int myz = 0; myz < 9; myz++) inv3(g[myz], g[9 + myz], g[18 + myz], ux);
+#pragma unroll
+    for (int cx = 0; cx < 3; cx++)
+#pragma unroll
+      for (int mz = 0; mz < 3; mz++)
+        inv3(g[cx * 9 + 0 + mz], g[cx * 9 + 3 + mz], g[cx * 9 + 6 + mz], uy);
+#pragma unroll
+    for (int cxy = 0; cxy < 9; cxy++) inv3(g[cxy * 3 + 0], g[cxy * 3 + 1], g[cxy * 3 + 2], uz);
+  }
+}
+
+// Central-moment equilibrium factor of one moment index (0 -> 1, 1 -> 0,
+// 2 -> cs^2 = 1/3): the equilibrium of moment (m,n,o) is psi * c(m) c(n) c(o),
+// i.e. psi at 000, psi cs^2 at 200/020/002, psi cs^4 at 220/202/022,
+// psi cs^6 at 222, zero elsewhere.
+template <class R>
+__host__ __device__ constexpr R ceq1(int m) {
+  return m == 0 ? R(1) : (m == 1 ? R(0) : R(1) / R(3));
+}
+
+// Relaxation toward the central-moment equilibrium, in place on the central
+// moments K (chimera order), rates s (chimera order).  psi is the conserved
+// zeroth moment used by the equilibrium; src the source of App. D (0 if none).
+template <int D, class R>
+__device__ __forceinline__ void relax(R *K, const R *s, R psi, R src) {
+  constexpr int NQ = D == 2 ? 9 : 27;
+#pragma unroll
+  for (int k = 0; k < NQ; k++) {
+    const int m = D == 2 ? k / 3 : k / 9;
+    const int n = D == 2 ? k % 3 : (k / 3) % 3;
+    const int o = D == 2 ? 0 : k % 3;
+    const R c = ceq1<R>(m) * ceq1<R>(n) * ceq1<R>(o);
+    if (c == R(0))
+      K[k] = K[k] - s[k] * K[k];
+    else
+      K[k] = K[k] + s[k] * (psi * c - K[k]);
+  }
+  K[0] += (R(1) - R(0.5) * s[0]) * src;
+}
+
+// Full central-moment collision of one lattice (chimera slots in, chimera
+// slots out): g* = T(u)^-1 [Y~ + S (Y~eq - Y~)].
+template <int D, class R>
+__device__ __forceinline__ void collide(R *g, const R *s, R ux, R uy, R uz, R src) {
+  to_central<D, R>(g, ux, uy, uz);
+  const R psi = g[0] + R(0.5) * src;
+  relax<D, R>(g, s, psi, src);
+  from_central<D, R>(g, ux, uy, uz);
+}
+
+// Discrete equilibrium of direction i in product form:
+// psi * prod_d phi(e_d, u_d), phi(0, u) = 2/3 - u^2, phi(+-1, u) = (1/3 + u^2 +- u)/2.
+template <class R>
+__device__ __forceinline__ R phi1(int c, R u) {
+  return c == 0 ? (R(2) / R(3) - u * u) : R(0.5) * (R(1) / R(3) + u * u + R(c) * u);
+}
+
+template <int Q, class R>
+__device__ __forceinline__ R geq_dir(int i, R psi, R ux, R uy, R uz) {
+  R v = psi * phi1<R>(Lat<Q>::ex(i), ux) * phi1<R>(Lat<Q>::ey(i), uy);
+  if constexpr (Lat<Q>::D == 3) v *= phi1<R>(Lat<Q>::ez(i), uz);
+  return v;
+}
+
+// Wall rules of Sec. 3.  q in (0, 1]; gb_i, gb_o: post-collision values of
+// the boundary node in the wall direction i and the opposite one; gf_i: the
+// post-collision value of x_f = x_b - e_i in direction i.
+template <class R>
+__device__ __forceinline__ R wall_ibb(R q, R gb_i, R gb_o, R gf_i) {
+  if (q <= R(0.5)) return R(2) * q * gb_i + (R(1) - R(2) * q) * gf_i;
+  return (gb_i + (R(2) * q - R(1)) * gb_o) / (R(2) * q);
+}
+
+template <class R>
+__device__ __forceinline__ R wall_iabb(R q, R gb_i, R gb_o, R gf_i, R geq_i) {
+  if (q <= R(0.5)) return -(R(2) * q * gb_i + (R(1) - R(2) * q) * gf_i) + R(2) * geq_i;
+  return (-gb_i + (R(2) * q - R(1)) * gb_o + R(2) * geq_i) / (R(2) * q);
+}
+
+}  // namespace lbm

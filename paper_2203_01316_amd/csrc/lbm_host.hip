@@ -1,0 +1,856 @@
+// lbm_host.hip -- C ABI of liblbm.so: parameter validation, relaxation
+// presets, workspace layout, geometry (cut-link table and boundary-node list)
+// and the calls that launch the kernels of lbm_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_device.hpp"
+#include "lbm_kernels.hpp"
+
+using namespace lbm;
+
+static_assert(sizeof(DevLink) == sizeof(lbm_link), "link layout");
+static_assert(sizeof(DevGroup) == sizeof(lbm_group), "group layout");
+
+namespace {
+
+thread_local std::string g_err;
+
+constexpr size_t kAlign = 256;
+constexpr int kPartials = 1024;  // blocks of the first reduction pass
+constexpr int kMaxColumns = 64;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Moment orders (per-moment rates are given in these orders): Sec. 2.1 for
+// D3Q27, App. A for D2Q9.
+const char *kMom27[27] = {"000", "100", "010", "001", "110", "101", "011", "200", "020",
+                          "002", "120", "102", "210", "201", "012", "021", "111", "220",
+                          "202", "022", "211", "121", "112", "122", "212", "221", "222"};
+const char *kMom9[9] = {"00", "10", "01", "20", "02", "11", "21", "12", "22"};
+
+void moment_index(int Q, int k, int m[3]) {
+  if (Q == 27) {
+    for (int d = 0; d < 3; d++) m[d] = kMom27[k][d] - '0';
+  } else {
+    m[0] = kMom9[k][0] - '0';
+    m[1] = kMom9[k][1] - '0';
+    m[2] = 0;
+  }
+}
+
+// Position of moment (m, n, o) in the kernels' chimera layout.
+int chimera_index(int Q, const int m[3]) { return Q == 27 ? m[0] * 9 + m[1] * 3 + m[2] : m[0] * 3 + m[1]; }
+
+struct Layout {
+  size_t pop_bytes;  // one copy of one lattice
+  size_t off_pop[2][2];
+  size_t off_cls, off_links, off_special, off_groups, off_rho, off_H, off_qx, off_flux, off_part,
+      off_res, off_cols;
+  size_t total;
+};
+
+size_t storage_size(int st) {
+  switch (st) {
+    case LBM_FP64: return 8;
+    case LBM_FP32:
+    case LBM_FP32_DEV: return 4;
+    case LBM_FP16_DEV: return 2;
+    default: return 0;
+  }
+}
+
+bool set_err(std::string *dst, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (dst) *dst = buf;
+  g_err = buf;
+  return false;
+}
+
+int64_t node_count(const lbm_params *p) { return (int64_t)p->nx * p->ny * p->nz; }
+
+bool validate(const lbm_params *p, std::string *err) {
+  if (!p) return set_err(err, "params is NULL");
+  if (p->lattice != LBM_D2Q9 && p->lattice != LBM_D3Q27)
+    return set_err(err, "lattice must be 9 (D2Q9) or 27 (D3Q27), got %d", p->lattice);
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+    return set_err(err, "nx, ny, nz must be >= 1 (got %d, %d, %d)", p->nx, p->ny, p->nz);
+  if (p->lattice == LBM_D2Q9 && p->nz != 1) return set_err(err, "D2Q9 needs nz == 1 (got %d)", p->nz);
+  if ((int64_t)p->nx * p->ny * p->nz > (int64_t)1 << 31)
+    return set_err(err, "too many nodes (%lld), limit 2^31", (long long)node_count(p));
+  if (storage_size(p->storage) == 0) return set_err(err, "unknown storage %d", p->storage);
+  if (p->stream != LBM_STREAM_AB)
+    return set_err(err, "stream mode %d not supported (only LBM_STREAM_AB)", p->stream);
+  if (p->with_ns != 0 && p->with_ns != 1) return set_err(err, "with_ns must be 0 or 1");
+  if (p->relax_h < LBM_CM_SRT || p->relax_h > LBM_CM_CUSTOM) return set_err(err, "unknown relax_h %d", p->relax_h);
+  if (p->with_ns && (p->relax_f < LBM_CM_SRT || p->relax_f > LBM_CM_CUSTOM))
+    return set_err(err, "unknown relax_f %d", p->relax_f);
+  if (p->relax_h != LBM_CM_CUSTOM && !(p->k > 0.0 && std::isfinite(p->k)))
+    return set_err(err, "conductivity k must be finite and > 0 (got %g)", p->k);
+  if (p->with_ns && p->relax_f != LBM_CM_CUSTOM && !(p->nu > 0.0 && std::isfinite(p->nu)))
+    return set_err(err, "viscosity nu must be finite and > 0 (got %g)", p->nu);
+  if (p->u_mode != 0 && p->u_mode != 1) return set_err(err, "u_mode must be 0 or 1");
+  if (p->with_source && p->with_ns) return set_err(err, "a source needs with_ns == 0");
+  if (p->max_links < 0 || p->max_special < 0) return set_err(err, "max_links/max_special must be >= 0");
+  for (int d = 0; d < 3; d++)
+    if (!std::isfinite(p->u0[d])) return set_err(err, "u0[%d] is not finite", d);
+  if (!std::isfinite(p->rho_ref) || !std::isfinite(p->H_ref)) return set_err(err, "rho_ref/H_ref not finite");
+  return true;
+}
+
+void preset_rates(const lbm_params *p, int relax, double rate, const double *custom, double *s) {
+  const int Q = p->lattice;
+  for (int k = 0; k < 27; k++) s[k] = 1.0;
+  for (int k = 0; k < Q; k++) {
+    int m[3];
+    moment_index(Q, k, m);
+    const int order = m[0] + m[1] + m[2];
+    switch (relax) {
+      case LBM_CM_SRT: s[k] = rate; break;
+      case LBM_CM_1ST: s[k] = order == 1 ? rate : 1.0; break;
+      case LBM_CM_TRT: s[k] = (order % 2 == 1) ? rate : 1.0; break;
+      case LBM_CM_NS: s[k] = order == 2 ? rate : 1.0; break;
+      default: s[k] = custom[k]; break;
+    }
+  }
+}
+
+void compute_rates(const lbm_params *p, double *sf, double *sh) {
+  const double s_nu = p->with_ns ? 1.0 / (3.0 * p->nu + 0.5) : 1.0;
+  const double s_H = p->relax_h == LBM_CM_CUSTOM ? 1.0 : 1.0 / (3.0 * p->k + 0.5);
+  preset_rates(p, p->with_ns ? p->relax_f : LBM_CM_NS, s_nu, p->s_custom_f, sf);
+  preset_rates(p, p->relax_h, s_H, p->s_custom_h, sh);
+}
+
+Layout layout(const lbm_params *p) {
+  Layout L;
+  const int64_t n = node_count(p);
+  const int Q = p->lattice;
+  size_t off = 0;
+  L.pop_bytes = align_up((size_t)Q * n * storage_size(p->storage));
+  for (int lat = 0; lat < 2; lat++)
+    for (int c = 0; c < 2; c++) {
+      const bool used = (lat == 1 || p->with_ns);
+      L.off_pop[lat][c] = off;
+      if (used) off += L.pop_bytes;
+    }
+  L.off_cls = off;
+  off += align_up((size_t)n);
+  L.off_links = off;
+  off += align_up(sizeof(DevLink) * (size_t)p->max_links);
+  L.off_special = off;
+  off += align_up(sizeof(DevSpecial) * (size_t)p->max_special);
+  L.off_groups = off;
+  off += align_up(sizeof(DevGroup) * LBM_MAX_GROUPS);
+  L.off_rho = off;
+  off += align_up(sizeof(double) * (size_t)n);
+  L.off_H = off;
+  off += align_up(sizeof(double) * (size_t)n);
+  L.off_qx = off;
+  off += align_up(sizeof(double) * (size_t)n);
+  L.off_flux = off;
+  off += align_up(sizeof(double) * (size_t)p->max_links);
+  L.off_part = off;
+  off += align_up(sizeof(double) * 2 * kPartials);
+  L.off_res = off;
+  off += align_up(sizeof(double) * (3 + kMaxColumns));
+  L.off_cols = off;
+  off += align_up(sizeof(int32_t) * kMaxColumns);
+  L.total = off;
+  return L;
+}
+
+// Geometry built on the host.
+struct Geometry {
+  std::vector<DevLink> links;
+  std::vector<DevSpecial> special;
+  std::vector<uint8_t> cls;
+  bool any = false;
+};
+
+int ntype(const uint16_t *flags, int64_t n) { return flags ? (flags[n] & 15) : 0; }
+int ngroup(const uint16_t *flags, int64_t n) { return flags ? ((flags[n] >> 4) & 255) : 0; }
+
+template <int Q>
+int64_t shift(const lbm_params *p, int64_t n, int i, int sign) {
+  const int64_t nx = p->nx, ny = p->ny, nz = p->nz;
+  int64_t x = n % nx, y = (n / nx) % ny, z = n / (nx * ny);
+  x = ((x + sign * Lat<Q>::ex(i)) % nx + nx) % nx;
+  y = ((y + sign * Lat<Q>::ey(i)) % ny + ny) % ny;
+  z = ((z + sign * Lat<Q>::ez(i)) % nz + nz) % nz;
+  return x + nx * (y + ny * z);
+}
+
+template <int Q>
+bool build_geometry_q(const lbm_params *p, const uint16_t *flags, const double *q, int n_groups,
+                      bool want_links, Geometry *G, int64_t *nlinks, int64_t *nspecial, std::string *err) {
+  const int64_t N = node_count(p);
+  int64_t cl = 0, cs = 0;
+  if (flags) {
+    for (int64_t n = 0; n < N; n++) {
+      const int t = flags[n] & 15;
+      if (t > 3) return set_err(err, "node %lld: unknown node type %d", (long long)n, t);
+      if (t != LBM_NODE_FLUID && t != LBM_NODE_OUTLET && ngroup(flags, n) >= n_groups)
+        return set_err(err, "node %lld: group %d >= n_groups %d", (long long)n, ngroup(flags, n), n_groups);
+    }
+  }
+  if (want_links) G->cls.assign(N, CLS_BULK);
+  auto links_of = [&](int64_t n, uint32_t *mask, bool emit) -> bool {
+    *mask = 0;
+    for (int i = 1; i < Q; i++) {
+      const int64_t w = shift<Q>(p, n, i, +1);
+      if (ntype(flags, w) != LBM_NODE_SOLID) continue;
+      const double qv = q ? q[(int64_t)i * N + n] : 0.5;
+      if (!(qv > 0.0 && qv <= 1.0))
+        return set_err(err, "cut link (node %lld, dir %d): q = %.17g outside (0, 1]", (long long)n, i, qv);
+      *mask |= 1u << i;
+      if (emit) {
+        DevLink L;
+        L.node = (int32_t)n;
+        L.dir = i;
+        L.group = ngroup(flags, w);
+        L.xf_solid = ntype(flags, shift<Q>(p, n, i, -1)) == LBM_NODE_SOLID;
+        L.q = qv;
+        G->links.push_back(L);
+      }
+    }
+    return true;
+  };
+  for (int64_t n = 0; flags && n < N; n++) {
+    const int t = ntype(flags, n);
+    if (t == LBM_NODE_SOLID) {
+      if (want_links) G->cls[n] = CLS_SOLID;
+      G->any = true;
+      continue;
+    }
+    uint32_t mask;
+    const int64_t lb = cl;
+    if (!links_of(n, &mask, want_links)) return false;
+    cl += __builtin_popcount(mask);
+    if (t == LBM_NODE_EQ || t == LBM_NODE_OUTLET || mask) {
+      G->any = true;
+      if (t == LBM_NODE_OUTLET) {
+        const int64_t x = n % p->nx;
+        const int64_t up = x == 0 ? n + p->nx - 1 : n - 1;
+        if (ntype(flags, up) == LBM_NODE_SOLID)
+          return set_err(err, "outlet node %lld: upstream node %lld is solid", (long long)n, (long long)up);
+      }
+      if (want_links) {
+        DevSpecial s;
+        memset(&s, 0, sizeof(s));
+        s.node = (int32_t)n;
+        s.type = t;
+        s.group = ngroup(flags, n);
+        s.lb = (int32_t)lb;
+        s.mask = mask;
+        G->special.push_back(s);
+        G->cls[n] = CLS_SPECIAL;
+      }
+      cs++;
+    }
+  }
+  if (want_links) {
+    // upstream link ranges of outlet nodes (links are sorted by node)
+    for (auto &s : G->special) {
+      if (s.type != LBM_NODE_OUTLET) continue;
+      const int64_t x = s.node % p->nx;
+      const int64_t up = x == 0 ? s.node + p->nx - 1 : s.node - 1;
+      size_t lo = 0, hi = G->links.size();
+      while (lo < hi) {
+        const size_t mid = (lo + hi) / 2;
+        if (G->links[mid].node < up) lo = mid + 1; else hi = mid;
+      }
+      uint32_t umask = 0;
+      for (size_t l = lo; l < G->links.size() && G->links[l].node == up; l++) umask |= 1u << G->links[l].dir;
+      s.ub = (int32_t)lo;
+      s.umask = umask;
+    }
+  }
+  if (nlinks) *nlinks = cl;
+  if (nspecial) *nspecial = cs;
+  return true;
+}
+
+bool build_geometry(const lbm_params *p, const uint16_t *flags, const double *q, int n_groups,
+                    bool want_links, Geometry *G, int64_t *nlinks, int64_t *nspecial, std::string *err) {
+  if (p->lattice == 9) return build_geometry_q<9>(p, flags, q, n_groups, want_links, G, nlinks, nspecial, err);
+  return build_geometry_q<27>(p, flags, q, n_groups, want_links, G, nlinks, nspecial, err);
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p;
+  int Q;
+  int64_t n;
+  hipStream_t stream;
+  int device;
+  char *ws;
+  Layout L;
+  int cur;  // copy holding the stored state
+  bool initialized;
+  bool geom;
+  int64_t nlinks, nspecial;
+  const void *uvel;
+  const void *src;
+  double sf[27], sh[27];  // moment order of the header
+  double sfc[27], shc[27];  // chimera order
+  int64_t t;
+  std::string err;
+  std::vector<DevLink> host_links;
+  std::vector<int32_t> host_cols;
+  // opt-in per-kernel timing: events around each bulk and boundary launch
+  std::vector<hipEvent_t> ev;
+  int64_t ev_used = 0;
+  bool profiling = false;
+  struct {
+    int64_t magic, t, Q, n, storage, with_ns, bytes, pad;
+  } hdr;
+  void *pop(int lat, int c) { return ws + L.off_pop[lat][c]; }
+};
+
+#define CTX_CHECK(ctx)                                                        \
+  do {                                                                        \
+    if (!(ctx)) {                                                             \
+      g_err = "context is NULL";                                              \
+      return LBM_EINVAL;                                                      \
+    }                                                                         \
+  } while (0)
+
+static lbm_status hip_fail(lbm_ctx *ctx, hipError_t e, const char *what) {
+  set_err(ctx ? &ctx->err : nullptr, "%s: %s", what, hipGetErrorString(e));
+  return LBM_EDEVICE;
+}
+
+#define HIP_TRY(ctx, expr, what)                 \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+  } while (0)
+
+static lbm_status activate(lbm_ctx *ctx) {
+  int d = -1;
+  if (hipGetDevice(&d) != hipSuccess || d != ctx->device)
+    HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  return LBM_OK;
+}
+
+static KArgs make_args(lbm_ctx *ctx, int src_copy) {
+  KArgs a;
+  memset(&a, 0, sizeof(a));
+  const bool ns = ctx->p.with_ns;
+  a.fsrc = ns ? ctx->pop(0, src_copy) : nullptr;
+  a.fdst = ns ? ctx->pop(0, src_copy ^ 1) : nullptr;
+  a.hsrc = ctx->pop(1, src_copy);
+  a.hdst = ctx->pop(1, src_copy ^ 1);
+  a.cls = ctx->geom ? reinterpret_cast<const uint8_t *>(ctx->ws + ctx->L.off_cls) : nullptr;
+  a.uvel = ctx->uvel;
+  a.with_uvel = ctx->uvel != nullptr;
+  a.src = ctx->p.with_source ? ctx->src : nullptr;
+  a.links = reinterpret_cast<const DevLink *>(ctx->ws + ctx->L.off_links);
+  a.special = reinterpret_cast<const DevSpecial *>(ctx->ws + ctx->L.off_special);
+  a.groups = reinterpret_cast<const DevGroup *>(ctx->ws + ctx->L.off_groups);
+  a.nspecial = ctx->geom ? ctx->nspecial : 0;
+  a.n = ctx->n;
+  a.nx = ctx->p.nx;
+  a.ny = ctx->p.ny;
+  a.nz = ctx->p.nz;
+  for (int k = 0; k < 27; k++) {
+    a.sf[k] = ctx->sfc[k];
+    a.sh[k] = ctx->shc[k];
+    a.sf32[k] = (float)ctx->sfc[k];
+    a.sh32[k] = (float)ctx->shc[k];
+  }
+  for (int d = 0; d < 3; d++) a.u0[d] = ctx->p.u0[d];
+  const bool dev = ctx->p.storage == LBM_FP32_DEV || ctx->p.storage == LBM_FP16_DEV;
+  a.fref = dev ? ctx->p.rho_ref : 0.0;
+  a.href = dev ? ctx->p.H_ref : 0.0;
+  return a;
+}
+
+static lbm_status run_pass(lbm_ctx *ctx, int mode, const KArgs &a) {
+  const bool timed = ctx->profiling && mode == MODE_STEP && ctx->ev_used + 3 <= (int64_t)ctx->ev.size();
+  if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[ctx->ev_used], ctx->stream), "event record");
+  HIP_TRY(ctx, launch_pass(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->geom, mode, a, ctx->stream),
+          "bulk kernel launch");
+  if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[ctx->ev_used + 1], ctx->stream), "event record");
+  if (ctx->geom)
+    HIP_TRY(ctx, launch_special(ctx->Q, ctx->p.storage, ctx->p.with_ns, mode, a, ctx->stream),
+            "boundary kernel launch");
+  if (timed) {
+    HIP_TRY(ctx, hipEventRecord(ctx->ev[ctx->ev_used + 2], ctx->stream), "event record");
+    ctx->ev_used += 3;
+  }
+  return LBM_OK;
+}
+
+static lbm_status need_ready(lbm_ctx *ctx) {
+  if (!ctx->initialized) {
+    set_err(&ctx->err, "state not initialised: call lbm_init_equilibrium or lbm_set_populations first");
+    return LBM_ESTATE;
+  }
+  if (!ctx->p.with_ns && ctx->p.u_mode == 1 && !ctx->uvel) {
+    set_err(&ctx->err, "u_mode = 1 but no velocity field set (lbm_set_velocity)");
+    return LBM_ESTATE;
+  }
+  if (ctx->p.with_source && !ctx->src) {
+    set_err(&ctx->err, "with_source = 1 but no source set (lbm_set_source)");
+    return LBM_ESTATE;
+  }
+  return LBM_OK;
+}
+
+extern "C" {
+
+const char *lbm_version(void) { return "liblbm 0.1 (gfx950, central-moment LBM)"; }
+
+size_t lbm_workspace_bytes(const lbm_params *p) {
+  if (!validate(p, nullptr)) return 0;
+  return layout(p).total;
+}
+
+lbm_status lbm_relaxation_rates(const lbm_params *p, double *s_f, double *s_h) {
+  if (!validate(p, nullptr)) return LBM_EINVAL;
+  double a[27], b[27];
+  compute_rates(p, a, b);
+  if (s_f) memcpy(s_f, a, sizeof(a));
+  if (s_h) memcpy(s_h, b, sizeof(b));
+  return LBM_OK;
+}
+
+lbm_status lbm_count_geometry(const lbm_params *p, const uint16_t *flags, int64_t *n_links,
+                              int64_t *n_special) {
+  if (!validate(p, nullptr)) return LBM_EINVAL;
+  Geometry G;
+  int64_t nl = 0, ns = 0;
+  if (!build_geometry(p, flags, nullptr, LBM_MAX_GROUPS, false, &G, &nl, &ns, nullptr)) return LBM_EINVAL;
+  if (n_links) *n_links = nl;
+  if (n_special) *n_special = ns;
+  return LBM_OK;
+}
+
+lbm_status lbm_build_links(const lbm_params *p, const uint16_t *flags, const double *q, int32_t n_groups,
+                           lbm_link *out, int64_t cap, int64_t *count) {
+  if (!validate(p, nullptr)) return LBM_EINVAL;
+  if (n_groups < 0 || n_groups > LBM_MAX_GROUPS) {
+    set_err(nullptr, "n_groups %d outside [0, %d]", n_groups, LBM_MAX_GROUPS);
+    return LBM_EINVAL;
+  }
+  Geometry G;
+  int64_t nl = 0, ns = 0;
+  if (!build_geometry(p, flags, q, n_groups, true, &G, &nl, &ns, nullptr)) return LBM_EINVAL;
+  if (count) *count = nl;
+  if (out)
+    for (int64_t i = 0; i < nl && i < cap; i++) memcpy(&out[i], &G.links[i], sizeof(lbm_link));
+  return LBM_OK;
+}
+
+const char *lbm_last_error(const lbm_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+lbm_status lbm_create(const lbm_params *p, void *workspace_dev, void *hip_stream, lbm_ctx **out) {
+  if (!out) {
+    g_err = "out is NULL";
+    return LBM_EINVAL;
+  }
+  *out = nullptr;
+  if (!validate(p, nullptr)) return LBM_EINVAL;
+  if (!workspace_dev || (reinterpret_cast<uintptr_t>(workspace_dev) % kAlign) != 0) {
+    set_err(nullptr, "workspace must be a non-NULL, %zu-byte aligned device pointer", kAlign);
+    return LBM_EINVAL;
+  }
+  lbm_ctx *ctx = new (std::nothrow) lbm_ctx();
+  if (!ctx) {
+    g_err = "out of host memory";
+    return LBM_ENOMEM;
+  }
+  ctx->p = *p;
+  ctx->Q = p->lattice;
+  ctx->n = node_count(p);
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    delete ctx;
+    g_err = "hipGetDevice failed";
+    return LBM_EDEVICE;
+  }
+  ctx->ws = static_cast<char *>(workspace_dev);
+  ctx->L = layout(p);
+  ctx->cur = 0;
+  ctx->initialized = false;
+  ctx->geom = false;
+  ctx->nlinks = ctx->nspecial = 0;
+  ctx->uvel = ctx->src = nullptr;
+  ctx->t = 0;
+  compute_rates(p, ctx->sf, ctx->sh);
+  for (int k = 0; k < 27; k++) ctx->sfc[k] = ctx->shc[k] = 1.0;
+  for (int k = 0; k < ctx->Q; k++) {
+    int m[3];
+    moment_index(ctx->Q, k, m);
+    ctx->sfc[chimera_index(ctx->Q, m)] = ctx->sf[k];
+    ctx->shc[chimera_index(ctx->Q, m)] = ctx->sh[k];
+  }
+  *out = ctx;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx *ctx) {
+  if (!ctx) return;
+  for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
+  delete ctx;
+}
+
+lbm_status lbm_set_geometry(lbm_ctx *ctx, const uint16_t *flags, const double *q, const lbm_group *groups,
+                            int32_t n_groups) {
+  CTX_CHECK(ctx);
+  if (n_groups < 0 || n_groups > LBM_MAX_GROUPS || (n_groups > 0 && !groups)) {
+    set_err(&ctx->err, "groups must hold n_groups in [0, %d] entries", LBM_MAX_GROUPS);
+    return LBM_EINVAL;
+  }
+  for (int g = 0; g < n_groups; g++) {
+    if (groups[g].f_scheme != LBM_WALL_BB && groups[g].f_scheme != LBM_WALL_IBB) {
+      set_err(&ctx->err, "group %d: unknown f_scheme %d", g, groups[g].f_scheme);
+      return LBM_EINVAL;
+    }
+    if (groups[g].h_scheme != LBM_WALL_ABB && groups[g].h_scheme != LBM_WALL_IABB) {
+      set_err(&ctx->err, "group %d: unknown h_scheme %d", g, groups[g].h_scheme);
+      return LBM_EINVAL;
+    }
+  }
+  Geometry G;
+  int64_t nl = 0, ns = 0;
+  if (!build_geometry(&ctx->p, flags, q, n_groups, true, &G, &nl, &ns, &ctx->err)) return LBM_EINVAL;
+  if (nl > ctx->p.max_links || ns > ctx->p.max_special) {
+    set_err(&ctx->err, "geometry has %lld cut links and %lld boundary nodes; capacity is max_links=%d, "
+            "max_special=%d", (long long)nl, (long long)ns, ctx->p.max_links, ctx->p.max_special);
+    return LBM_ENOMEM;
+  }
+  if (lbm_status st = activate(ctx)) return st;
+  std::vector<DevGroup> dg(LBM_MAX_GROUPS);
+  memset(dg.data(), 0, sizeof(DevGroup) * dg.size());
+  for (int g = 0; g < n_groups; g++) memcpy(&dg[g], &groups[g], sizeof(DevGroup));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->ws + ctx->L.off_groups, dg.data(), sizeof(DevGroup) * dg.size(),
+                              hipMemcpyHostToDevice, ctx->stream), "copy groups");
+  if (G.any) {
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->ws + ctx->L.off_cls, G.cls.data(), G.cls.size(), hipMemcpyHostToDevice,
+                                ctx->stream), "copy node classes");
+    if (nl)
+      HIP_TRY(ctx, hipMemcpyAsync(ctx->ws + ctx->L.off_links, G.links.data(), sizeof(DevLink) * nl,
+                                  hipMemcpyHostToDevice, ctx->stream), "copy links");
+    if (ns)
+      HIP_TRY(ctx, hipMemcpyAsync(ctx->ws + ctx->L.off_special, G.special.data(), sizeof(DevSpecial) * ns,
+                                  hipMemcpyHostToDevice, ctx->stream), "copy boundary nodes");
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "geometry upload");
+  ctx->geom = G.any;
+  ctx->nlinks = nl;
+  ctx->nspecial = ns;
+  ctx->host_links = std::move(G.links);
+  return LBM_OK;
+}
+
+lbm_status lbm_get_links(lbm_ctx *ctx, lbm_link *out, int64_t cap, int64_t *count) {
+  CTX_CHECK(ctx);
+  if (lbm_status st = activate(ctx)) return st;
+  if (count) *count = ctx->nlinks;
+  if (!out || cap <= 0 || ctx->nlinks == 0) return LBM_OK;
+  const int64_t m = cap < ctx->nlinks ? cap : ctx->nlinks;
+  HIP_TRY(ctx, hipMemcpyAsync(out, ctx->ws + ctx->L.off_links, sizeof(lbm_link) * m, hipMemcpyDeviceToHost,
+                              ctx->stream), "copy links to host");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "copy links to host");
+  return LBM_OK;
+}
+
+lbm_status lbm_set_velocity(lbm_ctx *ctx, const void *u_dev) {
+  CTX_CHECK(ctx);
+  ctx->uvel = u_dev;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_source(lbm_ctx *ctx, const void *Q_dev) {
+  CTX_CHECK(ctx);
+  if (!ctx->p.with_source) {
+    set_err(&ctx->err, "context was created with with_source = 0");
+    return LBM_EINVAL;
+  }
+  ctx->src = Q_dev;
+  return LBM_OK;
+}
+
+lbm_status lbm_init_equilibrium(lbm_ctx *ctx, const double *rho_dev, const double *u_dev, const double *H_dev) {
+  CTX_CHECK(ctx);
+  if (!H_dev) {
+    set_err(&ctx->err, "H must not be NULL");
+    return LBM_EINVAL;
+  }
+  if (lbm_status st = activate(ctx)) return st;
+  InitArgs a;
+  memset(&a, 0, sizeof(a));
+  ctx->cur = 0;
+  a.fdst = ctx->p.with_ns ? ctx->pop(0, 0) : nullptr;
+  a.hdst = ctx->pop(1, 0);
+  a.rho = rho_dev;
+  a.u = u_dev;
+  a.uvel = (!ctx->p.with_ns && ctx->p.u_mode == 1) ? ctx->uvel : nullptr;
+  if (!u_dev && !ctx->p.with_ns && ctx->p.u_mode == 1 && !ctx->uvel) {
+    set_err(&ctx->err, "u_mode = 1: set the velocity field before lbm_init_equilibrium or pass u");
+    return LBM_ESTATE;
+  }
+  a.H = H_dev;
+  a.n = ctx->n;
+  a.nx = ctx->p.nx;
+  a.ny = ctx->p.ny;
+  a.nz = ctx->p.nz;
+  for (int d = 0; d < 3; d++) a.u0[d] = ctx->p.u0[d];
+  const bool dev = ctx->p.storage == LBM_FP32_DEV || ctx->p.storage == LBM_FP16_DEV;
+  a.fref = dev ? ctx->p.rho_ref : 0.0;
+  a.href = dev ? ctx->p.H_ref : 0.0;
+  HIP_TRY(ctx, launch_init(ctx->Q, ctx->p.storage, ctx->p.with_ns, a, ctx->stream), "init kernel launch");
+  ctx->t = 0;
+  ctx->initialized = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx *ctx, int32_t nsteps) {
+  CTX_CHECK(ctx);
+  if (nsteps < 0) {
+    set_err(&ctx->err, "nsteps must be >= 0 (got %d)", nsteps);
+    return LBM_EINVAL;
+  }
+  if (lbm_status st = need_ready(ctx)) return st;
+  if (lbm_status st = activate(ctx)) return st;
+  for (int s = 0; s < nsteps; s++) {
+    KArgs a = make_args(ctx, ctx->cur);
+    if (lbm_status st = run_pass(ctx, MODE_STEP, a)) return st;
+    ctx->cur ^= 1;
+    ctx->t++;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_macroscopic(lbm_ctx *ctx, double *rho_dev, double *u_dev, double *H_dev) {
+  CTX_CHECK(ctx);
+  if (lbm_status st = need_ready(ctx)) return st;
+  if (lbm_status st = activate(ctx)) return st;
+  KArgs a = make_args(ctx, ctx->cur);
+  a.out0 = rho_dev;
+  a.out1 = u_dev;
+  a.out2 = H_dev;
+  a.out3 = nullptr;
+  a.link_flux = reinterpret_cast<double *>(ctx->ws + ctx->L.off_flux);
+  return run_pass(ctx, MODE_MACRO, a);
+}
+
+lbm_status lbm_get_populations(lbm_ctx *ctx, int32_t lattice, int32_t which, double *dst_dev) {
+  CTX_CHECK(ctx);
+  if (lattice != 0 && lattice != 1) {
+    set_err(&ctx->err, "lattice must be 0 (f) or 1 (h), got %d", lattice);
+    return LBM_EINVAL;
+  }
+  if (lattice == 0 && !ctx->p.with_ns) {
+    set_err(&ctx->err, "no f lattice (with_ns = 0)");
+    return LBM_EINVAL;
+  }
+  if ((which != 0 && which != 1) || !dst_dev) {
+    set_err(&ctx->err, "which must be 0 (pre-collision) or 1 (stored post-collision), dst non-NULL");
+    return LBM_EINVAL;
+  }
+  if (lbm_status st = need_ready(ctx)) return st;
+  if (lbm_status st = activate(ctx)) return st;
+  const bool dev = ctx->p.storage == LBM_FP32_DEV || ctx->p.storage == LBM_FP16_DEV;
+  if (which == 1) {
+    const double ref = dev ? (lattice == 0 ? ctx->p.rho_ref : ctx->p.H_ref) : 0.0;
+    HIP_TRY(ctx, launch_convert(ctx->Q, ctx->p.storage, false, ctx->pop(lattice, ctx->cur), dst_dev, ctx->n, ref,
+                                ctx->stream), "convert kernel launch");
+    return LBM_OK;
+  }
+  KArgs a = make_args(ctx, ctx->cur);
+  a.out0 = lattice == 0 ? dst_dev : nullptr;
+  a.out1 = lattice == 1 ? dst_dev : nullptr;
+  return run_pass(ctx, MODE_PRE, a);
+}
+
+lbm_status lbm_set_populations(lbm_ctx *ctx, int32_t lattice, const double *src_dev, int64_t t) {
+  CTX_CHECK(ctx);
+  if ((lattice != 0 && lattice != 1) || (lattice == 0 && !ctx->p.with_ns) || !src_dev) {
+    set_err(&ctx->err, "invalid lattice %d or NULL source", lattice);
+    return LBM_EINVAL;
+  }
+  if (lbm_status st = activate(ctx)) return st;
+  const bool dev = ctx->p.storage == LBM_FP32_DEV || ctx->p.storage == LBM_FP16_DEV;
+  const double ref = dev ? (lattice == 0 ? ctx->p.rho_ref : ctx->p.H_ref) : 0.0;
+  HIP_TRY(ctx, launch_convert(ctx->Q, ctx->p.storage, true, src_dev, ctx->pop(lattice, ctx->cur), ctx->n, ref,
+                              ctx->stream), "convert kernel launch");
+  ctx->t = t;
+  ctx->initialized = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32_t n_columns, double *out,
+                      int32_t nout) {
+  CTX_CHECK(ctx);
+  if (n_columns < 0 || n_columns > kMaxColumns || (n_columns > 0 && !columns)) {
+    set_err(&ctx->err, "n_columns must be in [0, %d]", kMaxColumns);
+    return LBM_EINVAL;
+  }
+  if (!out || nout < 3 + n_columns) {
+    set_err(&ctx->err, "out needs at least 3 + n_columns = %d entries", 3 + n_columns);
+    return LBM_EINVAL;
+  }
+  for (int j = 0; j < n_columns; j++)
+    if (columns[j] < 0 || columns[j] >= ctx->p.nx) {
+      set_err(&ctx->err, "columns[%d] = %d outside [0, nx)", j, columns[j]);
+      return LBM_EINVAL;
+    }
+  if (lbm_status st = need_ready(ctx)) return st;
+  if (lbm_status st = activate(ctx)) return st;
+  double *rho = reinterpret_cast<double *>(ctx->ws + ctx->L.off_rho);
+  double *H = reinterpret_cast<double *>(ctx->ws + ctx->L.off_H);
+  double *qx = reinterpret_cast<double *>(ctx->ws + ctx->L.off_qx);
+  double *flux = reinterpret_cast<double *>(ctx->ws + ctx->L.off_flux);
+  double *res = reinterpret_cast<double *>(ctx->ws + ctx->L.off_res);
+  int32_t *cols = reinterpret_cast<int32_t *>(ctx->ws + ctx->L.off_cols);
+  KArgs a = make_args(ctx, ctx->cur);
+  a.out0 = ctx->p.with_ns ? rho : nullptr;
+  a.out2 = H;
+  a.out3 = qx;
+  a.link_flux = flux;
+  if (lbm_status st = run_pass(ctx, MODE_MACRO, a)) return st;
+  ctx->host_cols.assign(columns, columns + n_columns);
+  if (n_columns)
+    HIP_TRY(ctx, hipMemcpyAsync(cols, ctx->host_cols.data(), sizeof(int32_t) * n_columns, hipMemcpyHostToDevice,
+                                ctx->stream), "copy columns");
+  HIP_TRY(ctx, launch_reduce(ctx->p.with_ns ? rho : nullptr, H, qx, ctx->n, ctx->p.nx, ctx->p.ny, ctx->p.nz, cols,
+                             n_columns, flux, reinterpret_cast<const DevLink *>(ctx->ws + ctx->L.off_links),
+                             ctx->geom ? ctx->nlinks : 0, group, reinterpret_cast<double *>(ctx->ws + ctx->L.off_part),
+                             kPartials, res, ctx->stream), "reduction launch");
+  double host[3 + kMaxColumns];
+  HIP_TRY(ctx, hipMemcpyAsync(host, res, sizeof(double) * (3 + n_columns), hipMemcpyDeviceToHost, ctx->stream),
+          "copy reductions");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "reduction");
+  memcpy(out, host, sizeof(double) * (3 + n_columns));
+  if (!std::isfinite(out[0]) || !std::isfinite(out[1])) {
+    set_err(&ctx->err, "non-finite mass or energy sum (mass %g, energy %g) at t = %lld", out[0], out[1],
+            (long long)ctx->t);
+    return LBM_EDIVERGED;
+  }
+  return LBM_OK;
+}
+
+size_t lbm_state_bytes(const lbm_ctx *ctx) {
+  if (!ctx) return 0;
+  const int lat = ctx->p.with_ns ? 2 : 1;
+  return kAlign + (size_t)lat * ctx->L.pop_bytes;
+}
+
+lbm_status lbm_save_state(lbm_ctx *ctx, void *dst_dev) {
+  CTX_CHECK(ctx);
+  if (!dst_dev) {
+    set_err(&ctx->err, "dst is NULL");
+    return LBM_EINVAL;
+  }
+  if (lbm_status st = need_ready(ctx)) return st;
+  if (lbm_status st = activate(ctx)) return st;
+  ctx->hdr.magic = 0x4c424d5354415445LL;
+  ctx->hdr.t = ctx->t;
+  ctx->hdr.Q = ctx->Q;
+  ctx->hdr.n = ctx->n;
+  ctx->hdr.storage = ctx->p.storage;
+  ctx->hdr.with_ns = ctx->p.with_ns;
+  ctx->hdr.bytes = (int64_t)lbm_state_bytes(ctx);
+  char *d = static_cast<char *>(dst_dev);
+  HIP_TRY(ctx, hipMemcpyAsync(d, &ctx->hdr, sizeof(ctx->hdr), hipMemcpyHostToDevice, ctx->stream), "save header");
+  size_t off = kAlign;
+  for (int lat = ctx->p.with_ns ? 0 : 1; lat < 2; lat++) {
+    HIP_TRY(ctx, hipMemcpyAsync(d + off, ctx->pop(lat, ctx->cur), ctx->L.pop_bytes, hipMemcpyDeviceToDevice,
+                                ctx->stream), "save populations");
+    off += ctx->L.pop_bytes;
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "save state");
+  return LBM_OK;
+}
+
+lbm_status lbm_load_state(lbm_ctx *ctx, const void *src_dev) {
+  CTX_CHECK(ctx);
+  if (!src_dev) {
+    set_err(&ctx->err, "src is NULL");
+    return LBM_EINVAL;
+  }
+  if (lbm_status st = activate(ctx)) return st;
+  decltype(ctx->hdr) h;
+  HIP_TRY(ctx, hipMemcpyAsync(&h, src_dev, sizeof(h), hipMemcpyDeviceToHost, ctx->stream), "load header");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "load header");
+  if (h.magic != 0x4c424d5354415445LL || h.Q != ctx->Q || h.n != ctx->n || h.storage != ctx->p.storage ||
+      h.with_ns != ctx->p.with_ns || h.bytes != (int64_t)lbm_state_bytes(ctx)) {
+    set_err(&ctx->err, "snapshot does not match this context (lattice, size, storage or lattices differ)");
+    return LBM_EINVAL;
+  }
+  const char *s = static_cast<const char *>(src_dev);
+  size_t off = kAlign;
+  for (int lat = ctx->p.with_ns ? 0 : 1; lat < 2; lat++) {
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->pop(lat, ctx->cur), s + off, ctx->L.pop_bytes, hipMemcpyDeviceToDevice,
+                                ctx->stream), "load populations");
+    off += ctx->L.pop_bytes;
+  }
+  ctx->t = h.t;
+  ctx->initialized = true;
+  return LBM_OK;
+}
+
+int64_t lbm_time(const lbm_ctx *ctx) { return ctx ? ctx->t : -1; }
+
+lbm_status lbm_profile_begin(lbm_ctx *ctx, int32_t max_steps) {
+  CTX_CHECK(ctx);
+  if (max_steps < 0 || max_steps > (1 << 20)) {
+    set_err(&ctx->err, "max_steps must be in [0, 2^20]");
+    return LBM_EINVAL;
+  }
+  if (lbm_status st = activate(ctx)) return st;
+  const size_t need = 3 * (size_t)max_steps;
+  while (ctx->ev.size() < need) {
+    hipEvent_t e;
+    HIP_TRY(ctx, hipEventCreate(&e), "hipEventCreate");
+    ctx->ev.push_back(e);
+  }
+  ctx->ev_used = 0;
+  ctx->profiling = max_steps > 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_profile_end(lbm_ctx *ctx, double *bulk_ms, double *boundary_ms, int64_t *steps) {
+  CTX_CHECK(ctx);
+  if (lbm_status st = activate(ctx)) return st;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "stream synchronise");
+  double b = 0.0, s = 0.0;
+  for (int64_t i = 0; i + 3 <= ctx->ev_used; i += 3) {
+    float t0 = 0.f, t1 = 0.f;
+    HIP_TRY(ctx, hipEventElapsedTime(&t0, ctx->ev[i], ctx->ev[i + 1]), "hipEventElapsedTime");
+    HIP_TRY(ctx, hipEventElapsedTime(&t1, ctx->ev[i + 1], ctx->ev[i + 2]), "hipEventElapsedTime");
+    b += t0;
+    s += t1;
+  }
+  if (bulk_ms) *bulk_ms = b;
+  if (boundary_ms) *boundary_ms = s;
+  if (steps) *steps = ctx->ev_used / 3;
+  ctx->profiling = false;
+  ctx->ev_used = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_sync(lbm_ctx *ctx) {
+  CTX_CHECK(ctx);
+  if (lbm_status st = activate(ctx)) return st;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "stream synchronise");
+  return LBM_OK;
+}
+
+}  // extern "C"

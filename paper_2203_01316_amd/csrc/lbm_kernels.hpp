@@ -1,0 +1,107 @@
+// lbm_kernels.hpp -- HIP kernels of the fused central-moment stream-and-collide
+// step and their launchers (instantiated in lbm_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Device copy of one cut link; same layout as lbm_link.
+struct DevLink {
+  int32_t node;
+  int32_t dir;
+  int32_t group;
+  int32_t xf_solid;
+  double q;
+};
+
+// Boundary node handled by the boundary kernel: EQ and OUTLET nodes and
+// non-solid nodes with at least one cut link.  Links of a node are stored
+// contiguously from lb in increasing direction, one per set bit of mask.
+// ub/umask give the links of the upstream (x - 1) node of an OUTLET node.
+struct DevSpecial {
+  int32_t node;
+  int32_t type;
+  int32_t group;
+  int32_t lb;
+  uint32_t mask;
+  int32_t ub;
+  uint32_t umask;
+  int32_t pad;
+};
+
+// Same layout as lbm_group.
+struct DevGroup {
+  int32_t f_scheme;
+  int32_t h_scheme;
+  double rho_w;
+  double u_w[3];
+  double H_w;
+};
+
+enum : int { NODE_FLUID = 0, NODE_SOLID = 1, NODE_EQ = 2, NODE_OUTLET = 3 };
+enum : uint8_t { CLS_BULK = 0, CLS_SOLID = 1, CLS_SPECIAL = 2 };
+
+// What a pass over the lattice produces.
+enum : int {
+  MODE_STEP = 0,  // collide and store the post-collision state (next buffer)
+  MODE_PRE = 1,   // write the canonical pre-collision state as FP64 [Q][n]
+  MODE_MACRO = 2  // write rho, u, H (and the x-flux of h) as FP64 fields
+};
+
+struct KArgs {
+  const void *fsrc;
+  void *fdst;
+  const void *hsrc;
+  void *hdst;
+  const uint8_t *cls;      // node classes, or null when there is no geometry
+  const void *uvel;        // [3][n] arithmetic type, or null
+  const void *src;         // [n] arithmetic type, or null
+  const DevLink *links;
+  const DevSpecial *special;
+  const DevGroup *groups;
+  int64_t nspecial;
+  int64_t n;
+  int32_t nx, ny, nz;
+  int32_t with_uvel;       // advection velocity from the field (else u0)
+  double sf[27];           // rates of f, chimera order
+  double sh[27];           // rates of h, chimera order
+  float sf32[27];          // the same rates rounded for FP32 arithmetic
+  float sh32[27];
+  double u0[3];
+  double fref, href;       // deviation references (0 unless *_DEV storage)
+  double *out0, *out1, *out2, *out3;  // MODE_PRE / MODE_MACRO outputs
+  double *link_flux;       // MODE_MACRO: per-link injected energy
+};
+
+struct InitArgs {
+  void *fdst;
+  void *hdst;
+  const double *rho;  // [n] or null (= 1)
+  const double *u;    // [3][n] or null
+  const void *uvel;   // fallback field, arithmetic type, or null
+  const double *H;    // [n]
+  int64_t n;
+  int32_t nx, ny, nz;
+  double u0[3];
+  double fref, href;
+};
+
+// storage codes (lbm_storage)
+enum : int { ST_FP64 = 0, ST_FP32 = 1, ST_FP32_DEV = 2, ST_FP16_DEV = 3 };
+
+// Launchers; return hipSuccess or the launch error.
+hipError_t launch_pass(int Q, int storage, bool ns, bool geom, int mode, const KArgs &a,
+                       hipStream_t s);
+hipError_t launch_special(int Q, int storage, bool ns, int mode, const KArgs &a, hipStream_t s);
+hipError_t launch_init(int Q, int storage, bool ns, const InitArgs &a, hipStream_t s);
+hipError_t launch_convert(int Q, int storage, bool to_storage, const void *from, void *to, int64_t n,
+                          double ref, hipStream_t s);
+hipError_t launch_reduce(const double *rho, const double *H, const double *qx, int64_t n, int nx,
+                         int ny, int nz, const int32_t *cols, int ncols, const double *link_flux,
+                         const DevLink *links, int64_t nlinks, int group, double *partials,
+                         int npartials, double *out, hipStream_t s);
+hipError_t launch_copy(const void *src, void *dst, int64_t nbytes, hipStream_t s);
+
+}  // namespace lbm

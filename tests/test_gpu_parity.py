@@ -1,0 +1,268 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
+identical seeded inputs.  FP64 runs must agree to 1e-12 relative L2, FP32 runs
+to 1e-5, link tables bit for bit."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2203_01316_amd import workloads as W
+
+from gpu_common import f32, gpu_post, gpu_pre, pair, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU parity tests need a GPU"
+    from paper_2203_01316_amd import lbm
+    return lbm
+
+
+# ---------------------------------------------------------------------------
+# Advection-diffusion, periodic (Gaussian hill, 64^2 FP64)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("relax,steps", [("trt", 1000), ("srt", 300), ("1st", 300)])
+def test_gaussian_hill_fp64(L, oracle, relax, steps):
+    H0 = W.gaussian_hill(64, 8.0, 0.5, None, (0.05, 0.02), 0.01, 0.0)
+    g, o = pair(L, oracle, Q=9, dims=(64, 64, 1), relax_h=relax, k=0.01, u0=(0.05, 0.02, 0), H0=H0)
+    g.step(steps)
+    o.step(steps)
+    _, ho = o.pre()
+    assert rel_l2(gpu_pre(g), ho) < TOL64
+    assert rel_l2(gpu_post(g), o.post_h) < TOL64
+    _, _, Hg = g.macroscopic()
+    _, _, Ho = o.macroscopic()
+    assert rel_l2(Hg.cpu().numpy(), Ho) < TOL64
+    if relax == "trt":
+        ana = W.gaussian_hill(64, 8.0, 0.5, None, (0.05, 0.02), 0.01, float(steps))
+        assert rel_l2(Hg.cpu().numpy(), ana) < 3e-4
+
+
+def test_ragged_sizes_fp64(L, oracle):
+    """Sizes that do not fill a 256-node block, odd extents, velocity field."""
+    rng = np.random.default_rng(31)
+    for dims in ((5, 3, 1), (67, 29, 1), (257, 1, 1), (1, 19, 1)):
+        n = dims[0] * dims[1]
+        u = np.zeros((3, n))
+        u[:2] = rng.uniform(-0.05, 0.05, (2, n))
+        g, o = pair(L, oracle, Q=9, dims=dims, k=0.03, uvel=u, H0=1 + 0.1 * rng.uniform(size=n))
+        g.step(13)
+        o.step(13)
+        assert rel_l2(gpu_pre(g), o.pre()[1]) < TOL64, dims
+
+
+# ---------------------------------------------------------------------------
+# Channel with walls, inlet, outlet and an interpolated cylinder
+# ---------------------------------------------------------------------------
+def _channel(L, oracle, nx, ny, cx, cy, r, storage, k=0.005, oracle_init=True):
+    flags, q, groups, u = W.channel(nx, ny, cx, cy, r, 0.05)
+    return pair(L, oracle, Q=9, dims=(nx, ny, 1), storage=storage, k=k, uvel=u, flags=flags, q=q,
+                groups=groups, H0=np.zeros(nx * ny), oracle_init=oracle_init)
+
+
+def test_channel_links_bit_exact(L, oracle):
+    g, o = _channel(L, oracle, 1024, 256, 256, 128, 20, "fp32", oracle_init=False)
+    assert g.links().tobytes() == o.links().tobytes()
+    assert len(o.links()) > 6000
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_channel_small(L, oracle, storage, tol):
+    g, o = _channel(L, oracle, 160, 48, 40, 24, 7.5, storage)
+    g.step(600)
+    o.step(600)
+    assert rel_l2(gpu_pre(g), o.pre()[1]) < tol
+    cols = [10, 80, 150]
+    red = g.reduce(group=2, columns=cols)
+    _, ho, flux = o.pre(with_flux=True)
+    links = o.links()
+    _, _, Ho = o.macroscopic()
+    assert red[1] == pytest.approx(Ho.sum(), rel=tol)
+    assert red[2] == pytest.approx(flux[links["group"] == 2].sum(), rel=max(tol, 1e-11) * 10)
+    for j, X in enumerate(cols):
+        assert red[3 + j] == pytest.approx(o.section_flux(X, ho), rel=max(tol, 1e-11) * 10, abs=1e-12)
+
+
+def test_channel_full_size_one_step(L, oracle):
+    """1024x256 FP32 at full size: after 200 GPU steps, one more GPU step equals
+    the oracle's step from the same stored state, node by node."""
+    g, o = _channel(L, oracle, 1024, 256, 256, 128, 20, "fp32", oracle_init=False)
+    g.step(200)
+    post = gpu_post(g)
+    o.set_post(h=post, t=g.t)
+    g.step(1)
+    o.step(1)
+    assert rel_l2(gpu_post(g), o.post_h) < TOL32
+    assert rel_l2(gpu_pre(g), o.pre()[1]) < TOL32
+
+
+# ---------------------------------------------------------------------------
+# Coupled flow + heat with a heated cylinder (IBB / IABB, EQ inlet, outlet)
+# ---------------------------------------------------------------------------
+def _cylinder(L, oracle, nx, ny, r, storage, nu=0.04, k=0.06, oracle_init=True):
+    flags, q, groups, u, rho0, H0 = W.heated_cylinder(nx, ny, r, u_in=0.04, amp=1e-3, seed=0)
+    return pair(L, oracle, Q=9, dims=(nx, ny, 1), storage=storage, with_ns=True, nu=nu, k=k, uvel=u,
+                flags=flags, q=q, groups=groups, H0=H0, u_init=f32(u) if storage != "fp64" else u,
+                rho0=rho0, oracle_init=oracle_init)
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_cylinder_ns_ade_small(L, oracle, storage, tol):
+    g, o = _cylinder(L, oracle, 192, 96, 9.5, storage)
+    g.step(400)
+    o.step(400)
+    fo, ho = o.pre()
+    assert rel_l2(gpu_pre(g, "f"), fo) < tol
+    assert rel_l2(gpu_pre(g, "h"), ho) < tol
+    rg, ug, Hg = g.macroscopic()
+    ro, uo, Ho = o.macroscopic()
+    assert rel_l2(rg.cpu().numpy(), ro) < tol
+    assert rel_l2(ug.cpu().numpy()[:2], uo[:2]) < 50 * tol
+    red = g.reduce(group=1, columns=[5, 150])
+    _, _, flux = o.pre(with_flux=True)
+    lk = o.links()
+    assert red[0] == pytest.approx(ro.sum(), rel=tol)
+    assert red[2] == pytest.approx(flux[lk["group"] == 1].sum(), rel=max(tol, 1e-10) * 10)
+
+
+def test_cylinder_full_size_one_step(L, oracle):
+    """2048^2 coupled FP32 (the benchmark configuration): one GPU step equals
+    the oracle's step from the same stored state at every node."""
+    g, o = _cylinder(L, oracle, 2048, 2048, 64, "fp32", nu=0.0512, k=0.0512 / 0.71, oracle_init=False)
+    g.step(20)
+    o.set_post(f=gpu_post(g, "f"), h=gpu_post(g, "h"), t=g.t)
+    g.step(1)
+    o.step(1)
+    assert rel_l2(gpu_post(g, "f"), o.post_f) < TOL32
+    assert rel_l2(gpu_post(g, "h"), o.post_h) < TOL32
+    red = g.reduce(group=1, columns=[50, 1947])
+    assert np.all(np.isfinite(red))
+
+
+# ---------------------------------------------------------------------------
+# D3Q27 coupled (Taylor-Green vortex)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_d3q27_tgv_small(L, oracle, storage, tol):
+    Lb = 12
+    rho, u, H = W.taylor_green_3d(Lb, 0.04)
+    g, o = pair(L, oracle, Q=27, dims=(Lb, Lb, Lb), storage=storage, with_ns=True, nu=0.02, k=0.02, H0=H,
+                u_init=u, rho0=rho)
+    g.step(30)
+    o.step(30)
+    fo, ho = o.pre()
+    assert rel_l2(gpu_pre(g, "f"), fo) < tol
+    assert rel_l2(gpu_pre(g, "h"), ho) < tol
+
+
+def test_d3q27_full_size_sampled(L, oracle):
+    """256^3 FP32: one GPU step equals the oracle's node collision applied to
+    the pulled neighbourhood, on 2000 sampled nodes; mass is conserved."""
+    import torch
+    n1 = 256
+    rho, u, H = W.taylor_green_3d(n1, 0.04)
+    g = L.LBM(27, n1, n1, n1, with_ns=True, storage="fp32", nu=0.002, k=0.002, relax_h="trt")
+    g.init(H, u=u, rho=rho)
+    del rho, u, H
+    g.step(5)
+    m0 = g.reduce()[:2]
+    e, _, _ = oracle.lattice(27)
+    rng = np.random.default_rng(5)
+    nodes = rng.integers(0, n1 ** 3, 2000)
+    x, y, z = nodes % n1, (nodes // n1) % n1, nodes // (n1 * n1)
+    src = (((x[None] - e[:, 0:1]) % n1) + n1 * (((y[None] - e[:, 1:2]) % n1)
+                                                 + n1 * ((z[None] - e[:, 2:3]) % n1)))
+    rows = torch.arange(27, device=g.device)[:, None]
+    srct = torch.as_tensor(src, device=g.device)
+    nt = torch.as_tensor(nodes, device=g.device)
+    pf = g.populations("f", "post")[rows, srct].cpu().numpy()
+    ph = g.populations("h", "post")[rows, srct].cpu().numpy()
+    g.step(1)
+    qf = g.populations("f", "post")[:, nt].cpu().numpy()
+    qh = g.populations("h", "post")[:, nt].cpu().numpy()
+    m1 = g.reduce()[:2]
+    assert m1[0] == pytest.approx(m0[0], rel=1e-6) and m1[1] == pytest.approx(m0[1], rel=1e-6)
+    sf, sh = L.relaxation_rates(g.params)
+    of = np.zeros_like(qf)
+    oh = np.zeros_like(qh)
+    for j in range(len(nodes)):
+        r = pf[:, j].sum()
+        uu = (e.T.astype(float) @ pf[:, j]) / r
+        of[:, j] = oracle.collide_node(27, pf[:, j], uu, sf)
+        oh[:, j] = oracle.collide_node(27, ph[:, j], uu, sh)
+    assert rel_l2(qf, of) < TOL32
+    assert rel_l2(qh, oh) < TOL32
+
+
+# ---------------------------------------------------------------------------
+# Source term, state I/O, errors
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_source_term(L, oracle, storage, tol):
+    n1 = 48
+    src = 0.01 * np.random.default_rng(1).standard_normal(n1 * n1)
+    g, o = pair(L, oracle, Q=9, dims=(n1, n1, 1), storage=storage, k=0.01, u0=(0.03, 0, 0), src=src)
+    g.step(200)
+    o.step(200)
+    assert rel_l2(gpu_pre(g), o.pre()[1]) < tol
+    _, _, Hg = g.macroscopic()
+    _, _, Ho = o.macroscopic()
+    assert rel_l2(Hg.cpu().numpy(), Ho) < tol
+
+
+def test_checkpoint_restart_is_bitwise(L, oracle):
+    g, _ = _channel(L, oracle, 96, 32, 30, 16, 5.0, "fp32")
+    g.step(10)
+    snap = g.save_state()
+    g.step(25)
+    a = gpu_post(g)
+    g.load_state(snap)
+    assert g.t == 10
+    g.step(25)
+    assert np.array_equal(gpu_post(g), a)
+
+
+def test_set_populations_roundtrip(L, oracle):
+    g, o = pair(L, oracle, Q=9, dims=(40, 24, 1), k=0.02, u0=(0.02, 0.01, 0),
+                H0=1 + 0.1 * np.random.default_rng(2).uniform(size=960))
+    st = np.random.default_rng(3).uniform(0, 0.3, (9, 960))
+    g.set_populations("h", st, t=7)
+    assert g.t == 7
+    assert np.array_equal(gpu_post(g), st)
+    o.set_post(h=st, t=7)
+    g.step(5)
+    o.step(5)
+    assert rel_l2(gpu_pre(g), o.pre()[1]) < TOL64
+
+
+def test_state_errors(L):
+    g = L.LBM(9, 16, 16, k=0.01)
+    with pytest.raises(L.LBMError) as e:
+        g.step(1)
+    assert e.value.status == L.ESTATE
+    g2 = L.LBM(9, 16, 16, k=0.01, u_mode=1)
+    with pytest.raises(L.LBMError) as e:
+        g2.init(np.ones(256))
+    assert e.value.status == L.ESTATE
+    g.init(np.ones(256))
+    with pytest.raises(L.LBMError) as e:
+        g.reduce(columns=[16])
+    assert "columns[0]" in str(e.value)
+
+
+def test_divergence_is_reported(L):
+    """A rate outside the stable range blows the state up; the FP64 reduction
+    reports it as EDIVERGED instead of returning NaN sums."""
+    s = np.full(27, 2.9)
+    g = L.LBM(9, 16, 16, k=0.01, relax_h="custom", s_custom_h=s, u0=(0.1, 0.05, 0))
+    g.init(1 + 0.1 * np.random.default_rng(4).uniform(size=256))
+    g.step(2000)
+    with pytest.raises(L.LBMError) as e:
+        g.reduce()
+    assert e.value.status == L.EDIVERGED
