@@ -215,7 +215,8 @@ lbm_status lbm_macroscopic(lbm_ctx *ctx, double *rho_dev, double *u_dev, double 
 
 /* Population state as FP64 device arrays [Q][n]: which = 0 the canonical
  * (pre-collision) state at time t, which = 1 the stored post-collision state
- * of step t-1.  lattice 0 = f, 1 = h. */
+ * of step t-1.  lattice 0 = f, 1 = h.  Solid nodes carry no state and read
+ * as zeros. */
 lbm_status lbm_get_populations(lbm_ctx *ctx, int32_t lattice, int32_t which, double *dst_dev);
 
 /* Replaces the stored post-collision state (which = 1 layout) of one lattice

@@ -669,8 +669,9 @@ lbm_status lbm_get_populations(lbm_ctx *ctx, int32_t lattice, int32_t which, dou
   const bool dev = ctx->p.storage == LBM_FP32_DEV || ctx->p.storage == LBM_FP16_DEV;
   if (which == 1) {
     const double ref = dev ? (lattice == 0 ? ctx->p.rho_ref : ctx->p.H_ref) : 0.0;
+    const uint8_t *cls = ctx->geom ? reinterpret_cast<const uint8_t *>(ctx->ws + ctx->L.off_cls) : nullptr;
     HIP_TRY(ctx, launch_convert(ctx->Q, ctx->p.storage, false, ctx->pop(lattice, ctx->cur), dst_dev, ctx->n, ref,
-                                ctx->stream), "convert kernel launch");
+                                cls, ctx->stream), "convert kernel launch");
     return LBM_OK;
   }
   KArgs a = make_args(ctx, ctx->cur);
@@ -689,7 +690,7 @@ lbm_status lbm_set_populations(lbm_ctx *ctx, int32_t lattice, const double *src_
   const bool dev = ctx->p.storage == LBM_FP32_DEV || ctx->p.storage == LBM_FP16_DEV;
   const double ref = dev ? (lattice == 0 ? ctx->p.rho_ref : ctx->p.H_ref) : 0.0;
   HIP_TRY(ctx, launch_convert(ctx->Q, ctx->p.storage, true, src_dev, ctx->pop(lattice, ctx->cur), ctx->n, ref,
-                              ctx->stream), "convert kernel launch");
+                              nullptr, ctx->stream), "convert kernel launch");
   ctx->t = t;
   ctx->initialized = true;
   return LBM_OK;

@@ -176,16 +176,15 @@ __device__ __forceinline__ void finish_node(const KArgs &a, int64_t m, typename 
   }
 }
 
-// Solid node in the output modes: stored values (MODE_PRE) or zeros.
+// Solid nodes carry no state: the output modes report zeros for them.
 template <int Q, int ST, bool NS, int MODE>
 __device__ __forceinline__ void solid_node(const KArgs &a, int64_t m) {
   if constexpr (MODE == MODE_PRE) {
-    using R = typename StT<ST>::R;
 #pragma unroll
     for (int i = 0; i < Q; i++) {
       if constexpr (NS)
-        if (a.out0) a.out0[i * a.n + m] = double(ldp<Q, ST>(a.fsrc, i, a.n, m, R(a.fref)));
-      if (a.out1) a.out1[i * a.n + m] = double(ldp<Q, ST>(a.hsrc, i, a.n, m, R(a.href)));
+        if (a.out0) a.out0[i * a.n + m] = 0.0;
+      if (a.out1) a.out1[i * a.n + m] = 0.0;
     }
   } else if constexpr (MODE == MODE_MACRO) {
     if (a.out0) a.out0[m] = 0.0;
@@ -378,17 +377,20 @@ __global__ void __launch_bounds__(256) k_init(const InitArgs a) {
 }
 
 // FP64 [Q][n] <-> storage.
+// FP64 [Q][n] <-> storage.  Reading out, solid nodes (cls) report zeros.
 template <int Q, int ST, bool TO_STORAGE>
-__global__ void __launch_bounds__(256) k_convert(const void *from, void *to, int64_t n, double ref) {
+__global__ void __launch_bounds__(256) k_convert(const void *from, void *to, int64_t n, double ref,
+                                                 const uint8_t *cls) {
   using R = typename StT<ST>::R;
   const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (m >= n) return;
+  const bool solid = cls && cls[m] == CLS_SOLID;
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     if constexpr (TO_STORAGE)
       stp<Q, ST>(to, i, n, m, R(static_cast<const double *>(from)[i * n + m]), R(ref));
     else
-      static_cast<double *>(to)[i * n + m] = double(ldp<Q, ST>(from, i, n, m, R(ref)));
+      static_cast<double *>(to)[i * n + m] = solid ? 0.0 : double(ldp<Q, ST>(from, i, n, m, R(ref)));
   }
 }
 
@@ -564,18 +566,18 @@ hipError_t launch_init(int Q, int storage, bool ns, const InitArgs &a, hipStream
 
 template <int Q, int ST>
 static hipError_t convert_t(bool to_storage, const void *from, void *to, int64_t n, double ref,
-                            hipStream_t s) {
+                            const uint8_t *cls, hipStream_t s) {
   if (to_storage)
-    k_convert<Q, ST, true><<<blocks_for(n, 256), 256, 0, s>>>(from, to, n, ref);
+    k_convert<Q, ST, true><<<blocks_for(n, 256), 256, 0, s>>>(from, to, n, ref, cls);
   else
-    k_convert<Q, ST, false><<<blocks_for(n, 256), 256, 0, s>>>(from, to, n, ref);
+    k_convert<Q, ST, false><<<blocks_for(n, 256), 256, 0, s>>>(from, to, n, ref, cls);
   return hipGetLastError();
 }
 
 hipError_t launch_convert(int Q, int storage, bool to_storage, const void *from, void *to, int64_t n,
-                          double ref, hipStream_t s) {
-  if (Q == 9) LBM_DISPATCH_ST(storage, (convert_t<9, ST>(to_storage, from, to, n, ref, s)))
-  if (Q == 27) LBM_DISPATCH_ST(storage, (convert_t<27, ST>(to_storage, from, to, n, ref, s)))
+                          double ref, const uint8_t *cls, hipStream_t s) {
+  if (Q == 9) LBM_DISPATCH_ST(storage, (convert_t<9, ST>(to_storage, from, to, n, ref, cls, s)))
+  if (Q == 27) LBM_DISPATCH_ST(storage, (convert_t<27, ST>(to_storage, from, to, n, ref, cls, s)))
   return hipErrorInvalidValue;
 }
 

@@ -97,7 +97,7 @@ hipError_t launch_pass(int Q, int storage, bool ns, bool geom, int mode, const K
 hipError_t launch_special(int Q, int storage, bool ns, int mode, const KArgs &a, hipStream_t s);
 hipError_t launch_init(int Q, int storage, bool ns, const InitArgs &a, hipStream_t s);
 hipError_t launch_convert(int Q, int storage, bool to_storage, const void *from, void *to, int64_t n,
-                          double ref, hipStream_t s);
+                          double ref, const uint8_t *cls, hipStream_t s);
 hipError_t launch_reduce(const double *rho, const double *H, const double *qx, int64_t n, int nx,
                          int ny, int nz, const int32_t *cols, int ncols, const double *link_flux,
                          const DevLink *links, int64_t nlinks, int group, double *partials,

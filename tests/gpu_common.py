@@ -16,6 +16,14 @@ def f32(a):
     return np.asarray(a, dtype=np.float32).astype(np.float64)
 
 
+def fluid_only(arr, flags):
+    """Populations with solid nodes zeroed (solid nodes carry no state)."""
+    a = np.array(arr, dtype=np.float64, copy=True)
+    if flags is not None:
+        a[..., (np.asarray(flags).reshape(-1) & 15) == W.SOLID] = 0.0
+    return a
+
+
 def pair(L, O, *, Q, dims, storage="fp64", with_ns=False, relax_h="trt", nu=0.0, k=0.01, u0=(0, 0, 0),
          uvel=None, src=None, flags=None, q=None, groups=(), H0=None, u_init=None, rho0=None, oracle_init=True):
     """GPU context and oracle simulation over identical inputs, both at t = 0."""
