@@ -199,12 +199,21 @@ __device__ __forceinline__ void solid_node(const KArgs &a, int64_t m) {
 }
 
 // ---------------------------------------------------------------------------
-// Bulk kernel: one thread per node, 256 nodes (4 wavefronts) per block.
+// Bulk nodes: one thread per node, 256 nodes (4 wavefronts) per block.
 // ---------------------------------------------------------------------------
+// Workgroups of one dispatch go round-robin to the 8 XCDs (block b runs on
+// XCD b % 8), and each XCD has its own L2.  Mapping block b to tile
+// (b % 8) * per + b / 8 hands every XCD one contiguous slab of the lattice, so
+// the cache lines that neighbouring tiles share through the +-1 shifts of the
+// pull stay in one L2 instead of being fetched once per XCD.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
+  const int64_t per = nb / 8;
+  return b < per * 8 ? (b % 8) * per + b / 8 : b;
+}
+
 template <int Q, int ST, bool NS, bool GEOM, int MODE>
-__global__ void __launch_bounds__(256) k_bulk(const KArgs a) {
+__device__ __forceinline__ void bulk_node(const KArgs &a, int64_t m) {
   using R = typename StT<ST>::R;
-  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (m >= a.n) return;
   if constexpr (GEOM) {
     const uint8_t c = a.cls[m];
@@ -232,6 +241,12 @@ __global__ void __launch_bounds__(256) k_bulk(const KArgs a) {
     h[i] = ldp<Q, ST>(a.hsrc, i, a.n, src, R(a.href));
   }
   finish_node<Q, ST, NS, MODE>(a, m, f, h);
+}
+
+template <int Q, int ST, bool NS, bool GEOM, int MODE>
+__global__ void __launch_bounds__(256) k_bulk(const KArgs a) {
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  bulk_node<Q, ST, NS, GEOM, MODE>(a, tile * 256 + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -291,9 +306,8 @@ __device__ __forceinline__ void pull_links(const KArgs &a, int64_t m, int32_t lb
 }
 
 template <int Q, int ST, bool NS, int MODE>
-__global__ void __launch_bounds__(64) k_special(const KArgs a) {
+__device__ __forceinline__ void special_node(const KArgs &a, int64_t t) {
   using R = typename StT<ST>::R;
-  const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (t >= a.nspecial) return;
   const DevSpecial sp = a.special[t];
   const int64_t m = sp.node;
@@ -332,6 +346,25 @@ __global__ void __launch_bounds__(64) k_special(const KArgs a) {
     }
   }
   finish_node<Q, ST, NS, MODE>(a, m, f, h);
+}
+
+template <int Q, int ST, bool NS, int MODE>
+__global__ void __launch_bounds__(64) k_special(const KArgs a) {
+  special_node<Q, ST, NS, MODE>(a, (int64_t)blockIdx.x * 64 + threadIdx.x);
+}
+
+// One launch per step with geometry (D2Q9): the first `sblocks` blocks (a
+// multiple of 8, so the XCD of a bulk block is unchanged) take the boundary
+// nodes, whose long chains of dependent loads then overlap the bulk stream
+// instead of running after it.
+template <int Q, int ST, bool NS>
+__global__ void __launch_bounds__(256) k_fused(const KArgs a, int sblocks) {
+  if ((int)blockIdx.x < sblocks) {
+    special_node<Q, ST, NS, MODE_STEP>(a, (int64_t)blockIdx.x * 256 + threadIdx.x);
+    return;
+  }
+  const int64_t tile = xcd_tile(blockIdx.x - sblocks, gridDim.x - sblocks);
+  bulk_node<Q, ST, NS, true, MODE_STEP>(a, tile * 256 + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -470,31 +503,6 @@ __global__ void __launch_bounds__(256) k_column_sum(const double *qx, int nx, in
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-template <int Q, int ST, bool NS, bool GEOM>
-static hipError_t pass_t(int mode, const KArgs &a, hipStream_t s) {
-  const unsigned g = blocks_for(a.n, 256);
-  if (mode == MODE_STEP)
-    k_bulk<Q, ST, NS, GEOM, MODE_STEP><<<g, 256, 0, s>>>(a);
-  else if (mode == MODE_PRE)
-    k_bulk<Q, ST, NS, GEOM, MODE_PRE><<<g, 256, 0, s>>>(a);
-  else
-    k_bulk<Q, ST, NS, GEOM, MODE_MACRO><<<g, 256, 0, s>>>(a);
-  return hipGetLastError();
-}
-
-template <int Q, int ST, bool NS>
-static hipError_t special_t(int mode, const KArgs &a, hipStream_t s) {
-  if (a.nspecial == 0) return hipSuccess;
-  const unsigned g = blocks_for(a.nspecial, 64);
-  if (mode == MODE_STEP)
-    k_special<Q, ST, NS, MODE_STEP><<<g, 64, 0, s>>>(a);
-  else if (mode == MODE_PRE)
-    k_special<Q, ST, NS, MODE_PRE><<<g, 64, 0, s>>>(a);
-  else
-    k_special<Q, ST, NS, MODE_MACRO><<<g, 64, 0, s>>>(a);
-  return hipGetLastError();
-}
-
 #define LBM_DISPATCH_ST(ST_VAL, CALL) \
   switch (ST_VAL) {                   \
     case ST_FP64: {                   \
@@ -516,6 +524,43 @@ static hipError_t special_t(int mode, const KArgs &a, hipStream_t s) {
     default:                          \
       return hipErrorInvalidValue;    \
   }
+
+template <int Q, int ST, bool NS, bool GEOM>
+static hipError_t pass_t(int mode, const KArgs &a, hipStream_t s) {
+  const unsigned g = blocks_for(a.n, 256);
+  if (mode == MODE_STEP)
+    k_bulk<Q, ST, NS, GEOM, MODE_STEP><<<g, 256, 0, s>>>(a);
+  else if (mode == MODE_PRE)
+    k_bulk<Q, ST, NS, GEOM, MODE_PRE><<<g, 256, 0, s>>>(a);
+  else
+    k_bulk<Q, ST, NS, GEOM, MODE_MACRO><<<g, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int Q, int ST, bool NS>
+static hipError_t fused_t(const KArgs &a, hipStream_t s) {
+  const int sblocks = (int)((blocks_for(a.nspecial, 256) + 7) / 8 * 8);
+  k_fused<Q, ST, NS><<<blocks_for(a.n, 256) + sblocks, 256, 0, s>>>(a, sblocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(int storage, bool ns, const KArgs &a, hipStream_t s) {
+  if (ns) LBM_DISPATCH_ST(storage, (fused_t<9, ST, true>(a, s)))
+  LBM_DISPATCH_ST(storage, (fused_t<9, ST, false>(a, s)))
+}
+
+template <int Q, int ST, bool NS>
+static hipError_t special_t(int mode, const KArgs &a, hipStream_t s) {
+  if (a.nspecial == 0) return hipSuccess;
+  const unsigned g = blocks_for(a.nspecial, 64);
+  if (mode == MODE_STEP)
+    k_special<Q, ST, NS, MODE_STEP><<<g, 64, 0, s>>>(a);
+  else if (mode == MODE_PRE)
+    k_special<Q, ST, NS, MODE_PRE><<<g, 64, 0, s>>>(a);
+  else
+    k_special<Q, ST, NS, MODE_MACRO><<<g, 64, 0, s>>>(a);
+  return hipGetLastError();
+}
 
 template <int Q>
 static hipError_t pass_q(int storage, bool ns, bool geom, int mode, const KArgs &a, hipStream_t s) {

@@ -95,6 +95,8 @@ enum : int { ST_FP64 = 0, ST_FP32 = 1, ST_FP32_DEV = 2, ST_FP16_DEV = 3 };
 hipError_t launch_pass(int Q, int storage, bool ns, bool geom, int mode, const KArgs &a,
                        hipStream_t s);
 hipError_t launch_special(int Q, int storage, bool ns, int mode, const KArgs &a, hipStream_t s);
+// D2Q9 step with geometry: boundary and bulk nodes in one launch.
+hipError_t launch_fused(int storage, bool ns, const KArgs &a, hipStream_t s);
 hipError_t launch_init(int Q, int storage, bool ns, const InitArgs &a, hipStream_t s);
 hipError_t launch_convert(int Q, int storage, bool to_storage, const void *from, void *to, int64_t n,
                           double ref, const uint8_t *cls, hipStream_t s);
