@@ -77,6 +77,104 @@ def copy_ceiling(torch, dev, nbytes=2 << 30, reps=20):
     return 2 * nbytes / sec
 
 
+def time_steps(torch, g, steps, warmup):
+    """GPU seconds per step over `steps` back-to-back steps (events on the stream)."""
+    g.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / steps
+
+
+def leg_cylinder(torch, L, W, np, storage, nx, ny, steps):
+    nu = 0.04 * 128 / 100.0
+    flags, q, groups, u, rho0, H0 = W.heated_cylinder(nx, ny, 64, u_in=0.04, amp=1e-3, seed=0)
+    uf = np.asarray(u, np.float32)
+    g = L.LBM(L.D2Q9, nx, ny, with_ns=True, storage=storage, nu=nu, k=nu / 0.71, flags=flags, q=q,
+              groups=groups, rho_ref=1.0, H_ref=10.0)
+    g.set_velocity(uf)
+    g.init(H0, u=uf.astype(np.float64), rho=rho0)
+    sec = time_steps(torch, g, steps, 50)
+    bpn = 2 * 2 * 9 * (2 if storage == "fp16_dev" else 4)
+    mlups = nx * ny / sec / 1e6
+    return {"workload": f"d2q9_ns_ade_heated_cylinder_{nx}x{ny}", "storage": storage, "MLUPS": round(mlups, 1),
+            "bytes_per_node": bpn, "pct_hbm_roofline": round(100 * mlups * 1e6 * bpn / HBM_PEAK, 2),
+            "us_per_step": round(sec * 1e6, 2)}
+
+
+def leg_tgv(torch, L, W, storage, n1, steps):
+    rho, u, H = W.taylor_green_3d(n1, 0.04)
+    g = L.LBM(L.D3Q27, n1, n1, n1, with_ns=True, storage=storage, nu=0.002, k=0.002, relax_h="trt",
+              rho_ref=1.0, H_ref=1.0)
+    g.init(H, u=u, rho=rho)
+    del rho, u, H
+    sec = time_steps(torch, g, steps, 10)
+    red = g.reduce()
+    bpn = 2 * 2 * 27 * (2 if storage == "fp16_dev" else 4)
+    mlups = n1 ** 3 / sec / 1e6
+    out = {"workload": f"d3q27_ns_ade_taylor_green_{n1}^3", "storage": storage, "MLUPS": round(mlups, 1),
+           "bytes_per_node": bpn, "pct_hbm_roofline": round(100 * mlups * 1e6 * bpn / HBM_PEAK, 2),
+           "us_per_step": round(sec * 1e6, 2), "mass": red[0], "energy": red[1]}
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
+def leg_adjoint(torch, L, np, n1=512, steps=2000, interval=45):
+    """Adjoint/forward step-time ratio: 512^2 advection-diffusion with a source,
+    FP32 forward and FP32 adjoint, checkpoints every `interval` steps."""
+    from paper_2203_01316_amd.adjoint import source_objective
+
+    n = n1 * n1
+    src = 0.01 * np.random.Generator(np.random.PCG64(1)).standard_normal(n)
+    target = 1.0 + 0.01 * np.random.Generator(np.random.PCG64(2)).standard_normal(n)
+    g = L.LBM(L.D2Q9, n1, n1, storage="fp32", k=0.01, u0=(0.03, 0.0, 0.0), with_source=True)
+    H0 = np.ones(n)
+    out = {"workload": f"d2q9_ade_source_{n1}x{n1}", "steps": steps, "checkpoint_interval": interval}
+    for rec in (False, True):
+        q = torch.tensor(src, dtype=torch.float32, device=g.device, requires_grad=True)
+        source_objective(q, g, H0, target, 20, interval=5, recompute=rec).backward()  # warm-up
+        q = torch.tensor(src, dtype=torch.float32, device=g.device, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = source_objective(q, g, H0, target, steps, interval=interval, recompute=rec)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        key = "with_replay" if rec else "no_replay"
+        out[key] = {"forward_us_per_step": round((t1 - t0) / steps * 1e6, 2),
+                    "backward_us_per_step": round((t2 - t1) / steps * 1e6, 2),
+                    "ratio": round((t2 - t1) / (t1 - t0), 3)}
+    # kernel-only ratio: step kernel vs adjoint kernel, events around each region
+    g.set_source(src.astype(np.float32))
+    g.init(H0)
+    fwd = time_steps(torch, g, steps, 20)
+    lam = torch.zeros(9, n, dtype=torch.float32, device=g.device)
+    other = torch.empty_like(lam)
+    dq = torch.zeros(n, dtype=torch.float64, device=g.device)
+    for _ in range(20):
+        g.adjoint_step(lam, other, dq)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps // 2):
+        g.adjoint_step(lam, other, dq)
+        g.adjoint_step(other, lam, dq)
+    e1.record()
+    torch.cuda.synchronize()
+    adj = e0.elapsed_time(e1) / 1e3 / (2 * (steps // 2))
+    out["kernels"] = {"forward_us_per_step": round(fwd * 1e6, 2), "adjoint_us_per_step": round(adj * 1e6, 2),
+                      "ratio": round(adj / fwd, 3)}
+    return out
+
+
 def cpu_baseline(inputs, steps):
     from oracle import oracle as O
 
@@ -104,6 +202,7 @@ def main():
     ap.add_argument("--storage", default="fp32")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP16, D3Q27 and adjoint legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: only one GPU is supported in this build (got --gpus {args.gpus}); the kernel "
@@ -185,6 +284,13 @@ def main():
         "mass": red[0],
         "energy": red[1],
     }
+    if not args.no_extra:
+        del g
+        torch.cuda.empty_cache()
+        out["also"] = [leg_cylinder(torch, L, W, np, "fp16_dev", nx, ny, 1000),
+                       leg_tgv(torch, L, W, "fp32", 256, 100), leg_tgv(torch, L, W, "fp16_dev", 256, 100)]
+        out["adjoint"] = leg_adjoint(torch, L, np)
+        out["adjoint_forward_ratio"] = out["adjoint"]["no_replay"]["ratio"]
     if not args.no_cpu:
         inputs = (flags, q, groups, uf.astype(np.float64), rho0, H0, nx, ny, nu, k)
         out["cpu_baseline"] = cpu_baseline(inputs, args.cpu_steps)

@@ -235,6 +235,30 @@ lbm_status lbm_set_populations(lbm_ctx *ctx, int32_t lattice, const double *src_
 lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32_t n_columns,
                       double *out, int32_t nout);
 
+/* ---- discrete adjoint ----------------------------------------------------
+ * Reverse mode of the advection-diffusion step with a source Q (App. D) for
+ * contexts with with_ns = 0 and no geometry (fully periodic); other contexts
+ * return LBM_EUNSUPPORTED.  Not in the paper: the reverse step is the exact
+ * transpose of the forward step.  That step is affine in (state, Q) for a
+ * prescribed velocity, so the reverse step needs no forward state.
+ * lambda: adjoint of the canonical (pre-collision) state, device [Q][n] in
+ * the arithmetic type (double for LBM_FP64, float otherwise); dJdQ: device
+ * FP64 [n], an accumulator over all reverse steps. */
+
+/* Objective J = 1/2 sum_x (H(x) - H_target(x))^2 of the canonical state at the
+ * current time (H = sum h + Q/2).  Writes lambda = dJ/d(state) (every
+ * direction H - H_target), sets dJdQ = (H - H_target)/2 (the direct
+ * dependence through Q/2) and returns J (synchronises).  H_target: device
+ * FP64 [n]. */
+lbm_status lbm_objective(lbm_ctx *ctx, const double *H_target_dev, void *lambda_dev, void *dJdQ_dev,
+                         double *J);
+
+/* One reverse step: lambda_next = dJ/d(state at t+1) -> lambda_prev =
+ * dJ/d(state at t), and dJdQ += dJ/dQ through the collision of step t
+ * (may be NULL).  The two lambda buffers must be distinct.  Uses only the
+ * context's parameters and velocity field, not its population state. */
+lbm_status lbm_adjoint_step(lbm_ctx *ctx, const void *lambda_next_dev, void *lambda_prev_dev, void *dJdQ_dev);
+
 /* Bytes of a raw state snapshot (populations in storage layout + header). */
 size_t lbm_state_bytes(const lbm_ctx *ctx);
 

@@ -701,3 +701,87 @@ double ora_section_flux(const ora_cfg *c, const double *h, int X) {
     }
   return s;
 }
+
+/* ---------------------------------------------------------------------------
+ * Discrete adjoint of the advection-diffusion step (prescribed velocity,
+ * fully periodic lattice, optional source Q).  Not in the paper: defined as
+ * the exact transpose of the forward step above.
+ *
+ * Per node the collision is affine: g* = A g + b Q with
+ *   A = T^-1 [(1 - S) T + S ceq 1^T],   b = T^-1 [S ceq / 2 + (1 - s_000/2) e_000],
+ * where ceq is the central-moment equilibrium per unit psi and 1^T g = Y~_000.
+ * Streaming is the permutation pre_a(x) = post_a(x - e_a).
+ * With lam_pre(t+1) = dJ/dpre(t+1):
+ *   lam_post(t)_a(x) = lam_pre(t+1)_a(x + e_a)          (transpose of streaming)
+ *   lam_pre(t)       = A^T lam_post(t)                  (per node)
+ *   dJdQ(x)         += b^T lam_post(t)(x)
+ * A and b are assembled here as explicit matrices from T(u), M^-1, N(-u).
+ * ------------------------------------------------------------------------- */
+static void collision_matrix(const ora_ctx *C, const double u[3], const double *s, double *A,
+                             double *b) {
+  int Q = C->L.Q;
+  double T[ORA_MAXQ * ORA_MAXQ], Tinv[ORA_MAXQ * ORA_MAXQ], ceq[ORA_MAXQ];
+  double Nm[ORA_MAXQ * ORA_MAXQ], mu[3] = {-u[0], -u[1], -u[2]};
+  double K[ORA_MAXQ * ORA_MAXQ], v[ORA_MAXQ];
+  matrix_T(&C->L, u, T);
+  matrix_N(&C->L, mu, Nm);
+  /* T^-1 = M^-1 N(-u) */
+  for (int a = 0; a < Q; a++)
+    for (int k = 0; k < Q; k++) {
+      double acc = 0.0;
+      for (int j = 0; j < Q; j++) acc += C->Minv[a * Q + j] * Nm[j * Q + k];
+      Tinv[a * Q + k] = acc;
+    }
+  cm_equilibrium(&C->L, 1.0, ceq);
+  /* K = (1 - S) T + S ceq 1^T   (row k) */
+  for (int k = 0; k < Q; k++)
+    for (int a = 0; a < Q; a++) K[k * Q + a] = (1.0 - s[k]) * T[k * Q + a] + s[k] * ceq[k];
+  for (int a = 0; a < Q; a++)
+    for (int c = 0; c < Q; c++) {
+      double acc = 0.0;
+      for (int k = 0; k < Q; k++) acc += Tinv[a * Q + k] * K[k * Q + c];
+      A[a * Q + c] = acc;
+    }
+  for (int k = 0; k < Q; k++) v[k] = 0.5 * s[k] * ceq[k] + (k == 0 ? 1.0 - 0.5 * s[0] : 0.0);
+  for (int a = 0; a < Q; a++) {
+    double acc = 0.0;
+    for (int k = 0; k < Q; k++) acc += Tinv[a * Q + k] * v[k];
+    b[a] = acc;
+  }
+}
+
+int ora_collision_matrix(int Q, const double *u, const double *s, double *A, double *b) {
+  ora_ctx C;
+  if (ctx_init(Q, &C)) return -1;
+  collision_matrix(&C, u, s, A, b);
+  return 0;
+}
+
+/* One reverse step: lam_next = dJ/dpre(t+1) -> lam_prev = dJ/dpre(t), and
+ * dJdQ += dJ/dQ through the collision of step t.  Advection-only, no
+ * geometry. */
+int ora_adjoint_step(const ora_cfg *c, const double *lam_next, double *lam_prev, double *dJdQ) {
+  ora_ctx C;
+  long N;
+  if (check_cfg(c) || ctx_init(c->Q, &C) || c->with_ns || c->flags) return -1;
+  N = nnodes(c);
+#pragma omp parallel for schedule(static)
+  for (long n = 0; n < N; n++) {
+    int Q = c->Q;
+    double u[3], A[ORA_MAXQ * ORA_MAXQ], b[ORA_MAXQ], lp[ORA_MAXQ];
+    node_velocity_prescribed(c, n, u);
+    collision_matrix(&C, u, c->s_h, A, b);
+    for (int a = 0; a < Q; a++) lp[a] = lam_next[a * N + neighbour(c, n, C.L.e[a], +1)];
+    for (int a = 0; a < Q; a++) {
+      double acc = 0.0;
+      for (int k = 0; k < Q; k++) acc += A[k * Q + a] * lp[k];
+      lam_prev[a * N + n] = acc;
+    }
+    if (dJdQ) {
+      double acc = 0.0;
+      for (int a = 0; a < Q; a++) acc += b[a] * lp[a];
+      dJdQ[n] += acc;
+    }
+  }
+  return 0;
+}

@@ -111,6 +111,16 @@ def cm_equilibrium(Q: int, psi: float):
     return out
 
 
+def collision_matrix(Q: int, u, s):
+    """Per-node affine collision g* = A g + b Q (advection-diffusion)."""
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    ss = np.ascontiguousarray(s, dtype=np.float64)
+    A = np.zeros((Q, Q))
+    b = np.zeros(Q)
+    assert lib().ora_collision_matrix(Q, _p(uu), _p(ss), _p(A), _p(b)) == 0
+    return A, b
+
+
 def collide_node(Q: int, g, u, s, src: float = 0.0):
     g = np.ascontiguousarray(g, dtype=np.float64)
     uu = np.ascontiguousarray(u, dtype=np.float64)
@@ -284,6 +294,31 @@ class Sim:
         for i in range(n):
             out[i] = (arr[i].node, arr[i].dir, arr[i].group, arr[i].xf_solid, arr[i].q)
         return out
+
+    def adjoint_step(self, lam_next, dJdQ=None):
+        """lam_next = dJ/dpre(t+1) -> dJ/dpre(t); dJdQ (if given) accumulates."""
+        lam_next = np.ascontiguousarray(lam_next, dtype=np.float64).reshape(self.Q, self.N)
+        out = np.zeros_like(lam_next)
+        assert lib().ora_adjoint_step(C.byref(self.cfg), _p(lam_next), _p(out), _p(dJdQ)) == 0
+        return out
+
+    def objective(self, H_target):
+        """J = 1/2 sum (H - H*)^2 of the canonical state, dJ/dpre (all
+        directions equal H - H*) and the direct part of dJ/dQ (Q enters H as Q/2)."""
+        _, _, H = self.macroscopic()
+        r = H - np.asarray(H_target, dtype=np.float64).reshape(-1)
+        lam = np.repeat(r[None, :], self.Q, axis=0)
+        return 0.5 * float((r * r).sum()), lam, 0.5 * r
+
+    def gradient_source(self, H_target, steps):
+        """J and dJ/dQ after `steps` steps from the current post state (which
+        must be the initial one): forward, objective, then reverse steps."""
+        self.step(steps)
+        J, lam, dJdQ = self.objective(H_target)
+        dJdQ = np.ascontiguousarray(dJdQ)
+        for _ in range(steps):
+            lam = self.adjoint_step(lam, dJdQ)
+        return J, dJdQ
 
     def section_flux(self, X, h=None):
         if h is None:

@@ -178,6 +178,68 @@ __device__ __forceinline__ void from_central(R *g, R ux, R uy, R uz) {
   }
 }
 
+// Transposes of the one-axis transforms (reverse-mode of the collision).
+// fwd3_T: (K0, K1, K2) -> the transpose of fwd3 applied to them.
+template <class R>
+__device__ __forceinline__ void fwd3_T(R &a, R &b, R &c, R u) {
+  const R K0 = a, K1 = b, K2 = c;
+  const R up = R(1) + u, um = R(1) - u;
+  a = K0 - up * K1 + up * up * K2;
+  b = K0 - u * K1 + u * u * K2;
+  c = K0 + um * K1 + um * um * K2;
+}
+
+// inv3_T: transpose of inv3, populations (a, b, c) -> moment space.
+template <class R>
+__device__ __forceinline__ void inv3_T(R &a, R &b, R &c, R u) {
+  const R A = a, B = b, C = c;
+  a = R(0.5) * (u * u - u) * A + (R(1) - u * u) * B + R(0.5) * (u * u + u) * C;
+  b = (u - R(0.5)) * A - R(2) * u * B + (u + R(0.5)) * C;
+  c = R(0.5) * A - B + R(0.5) * C;
+}
+
+// T(u)^T: central-moment slots -> velocity slots (passes x, y, z).
+template <int D, class R>
+__device__ __forceinline__ void to_central_T(R *g, R ux, R uy, R uz) {
+  if constexpr (D == 2) {
+#pragma unroll
+    for (int my = 0; my < 3; my++) fwd3_T(g[0 + my], g[3 + my], g[6 + my], ux);
+#pragma unroll
+    for (int cx = 0; cx < 3; cx++) fwd3_T(g[cx * 3 + 0], g[cx * 3 + 1], g[cx * 3 + 2], uy);
+  } else {
+#pragma unroll
+    for (int myz = 0; myz < 9; myz++) fwd3_T(g[myz], g[9 + myz], g[18 + myz], ux);
+#pragma unroll
+    for (int cx = 0; cx < 3; cx++)
+#pragma unroll
+      for (int mz = 0; mz < 3; mz++)
+        fwd3_T(g[cx * 9 + 0 + mz], g[cx * 9 + 3 + mz], g[cx * 9 + 6 + mz], uy);
+#pragma unroll
+    for (int cxy = 0; cxy < 9; cxy++) fwd3_T(g[cxy * 3 + 0], g[cxy * 3 + 1], g[cxy * 3 + 2], uz);
+  }
+}
+
+// T(u)^-T: velocity slots -> central-moment slots (passes z, y, x).
+template <int D, class R>
+__device__ __forceinline__ void from_central_T(R *g, R ux, R uy, R uz) {
+  if constexpr (D == 2) {
+#pragma unroll
+    for (int cx = 0; cx < 3; cx++) inv3_T(g[cx * 3 + 0], g[cx * 3 + 1], g[cx * 3 + 2], uy);
+#pragma unroll
+    for (int my = 0; my < 3; my++) inv3_T(g[0 + my], g[3 + my], g[6 + my], ux);
+  } else {
+#pragma unroll
+    for (int cxy = 0; cxy < 9; cxy++) inv3_T(g[cxy * 3 + 0], g[cxy * 3 + 1], g[cxy * 3 + 2], uz);
+#pragma unroll
+    for (int cx = 0; cx < 3; cx++)
+#pragma unroll
+      for (int mz = 0; mz < 3; mz++)
+        inv3_T(g[cx * 9 + 0 + mz], g[cx * 9 + 3 + mz], g[cx * 9 + 6 + mz], uy);
+#pragma unroll
+    for (int myz = 0; myz < 9; myz++) inv3_T(g[myz], g[9 + myz], g[18 + myz], ux);
+  }
+}
+
 // Central-moment equilibrium factor of one moment index (0 -> 1, 1 -> 0,
 // 2 -> cs^2 = 1/3): the equilibrium of moment (m,n,o) is psi * c(m) c(n) c(o),
 // i.e. psi at 000, psi cs^2 at 200/020/002, psi cs^4 at 220/202/022,
@@ -215,6 +277,33 @@ __device__ __forceinline__ void collide(R *g, const R *s, R ux, R uy, R uz, R sr
   const R psi = g[0] + R(0.5) * src;
   relax<D, R>(g, s, psi, src);
   from_central<D, R>(g, ux, uy, uz);
+}
+
+// Reverse-mode of collide() for the advection-diffusion lattice, whose
+// collision is affine in (g, src) for a prescribed u:
+//   g* = A g + b src,  A = T^-1 [(1 - S) T + S ceq 1^T],
+//   b = T^-1 [S ceq / 2 + (1 - s_000/2) e_000].
+// In place: lam (velocity slots, adjoint of g*) -> A^T lam; returns b^T lam.
+// With mu = T^-T lam:  A^T lam = T^T [(1 - S) mu + e_000 (ceq . S mu)].
+template <int D, class R>
+__device__ __forceinline__ R collide_adjoint(R *g, const R *s, R ux, R uy, R uz) {
+  constexpr int NQ = D == 2 ? 9 : 27;
+  from_central_T<D, R>(g, ux, uy, uz);
+  R csm = 0;
+#pragma unroll
+  for (int k = 0; k < NQ; k++) {
+    const int m = D == 2 ? k / 3 : k / 9;
+    const int n = D == 2 ? k % 3 : (k / 3) % 3;
+    const int o = D == 2 ? 0 : k % 3;
+    const R c = ceq1<R>(m) * ceq1<R>(n) * ceq1<R>(o);
+    if (c != R(0)) csm += c * s[k] * g[k];
+  }
+  const R dq = R(0.5) * csm + (R(1) - R(0.5) * s[0]) * g[0];
+#pragma unroll
+  for (int k = 0; k < NQ; k++) g[k] = (R(1) - s[k]) * g[k];
+  g[0] += csm;
+  to_central_T<D, R>(g, ux, uy, uz);
+  return dq;
 }
 
 // Discrete equilibrium of direction i in product form:

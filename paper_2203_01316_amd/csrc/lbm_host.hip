@@ -52,7 +52,7 @@ int chimera_index(int Q, const int m[3]) { return Q == 27 ? m[0] * 9 + m[1] * 3 
 struct Layout {
   size_t pop_bytes;  // one copy of one lattice
   size_t off_pop[2][2];
-  size_t off_cls, off_links, off_special, off_groups, off_rho, off_H, off_qx, off_flux, off_part,
+  size_t off_cls, off_skip, off_links, off_special, off_groups, off_rho, off_H, off_qx, off_flux, off_part,
       off_res, off_cols;
   size_t total;
 };
@@ -147,6 +147,8 @@ Layout layout(const lbm_params *p) {
     }
   L.off_cls = off;
   off += align_up((size_t)n);
+  L.off_skip = off;
+  off += align_up(sizeof(uint32_t) * (size_t)((n + 31) / 32));
   L.off_links = off;
   off += align_up(sizeof(DevLink) * (size_t)p->max_links);
   L.off_special = off;
@@ -176,6 +178,7 @@ struct Geometry {
   std::vector<DevLink> links;
   std::vector<DevSpecial> special;
   std::vector<uint8_t> cls;
+  std::vector<uint32_t> skip;  // 1 bit per node: not a bulk node
   bool any = false;
 };
 
@@ -355,6 +358,7 @@ static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   a.hsrc = ctx->pop(1, src_copy);
   a.hdst = ctx->pop(1, src_copy ^ 1);
   a.cls = ctx->geom ? reinterpret_cast<const uint8_t *>(ctx->ws + ctx->L.off_cls) : nullptr;
+  a.skip = ctx->geom ? reinterpret_cast<const uint32_t *>(ctx->ws + ctx->L.off_skip) : nullptr;
   a.uvel = ctx->uvel;
   a.with_uvel = ctx->uvel != nullptr;
   a.src = ctx->p.with_source ? ctx->src : nullptr;
@@ -551,6 +555,11 @@ lbm_status lbm_set_geometry(lbm_ctx *ctx, const uint16_t *flags, const double *q
   HIP_TRY(ctx, hipMemcpyAsync(ctx->ws + ctx->L.off_groups, dg.data(), sizeof(DevGroup) * dg.size(),
                               hipMemcpyHostToDevice, ctx->stream), "copy groups");
   if (G.any) {
+    G.skip.assign((size_t)((ctx->n + 31) / 32), 0u);
+    for (int64_t m = 0; m < ctx->n; m++)
+      if (G.cls[m] != CLS_BULK) G.skip[m >> 5] |= 1u << (m & 31);
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->ws + ctx->L.off_skip, G.skip.data(), sizeof(uint32_t) * G.skip.size(),
+                                hipMemcpyHostToDevice, ctx->stream), "copy skip mask");
     HIP_TRY(ctx, hipMemcpyAsync(ctx->ws + ctx->L.off_cls, G.cls.data(), G.cls.size(), hipMemcpyHostToDevice,
                                 ctx->stream), "copy node classes");
     if (nl)
@@ -754,6 +763,59 @@ lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32
             (long long)ctx->t);
     return LBM_EDIVERGED;
   }
+  return LBM_OK;
+}
+
+static lbm_status need_adjoint(lbm_ctx *ctx) {
+  if (ctx->p.with_ns || ctx->geom) {
+    set_err(&ctx->err, "the adjoint is built for advection-only contexts without geometry (periodic)");
+    return LBM_EUNSUPPORTED;
+  }
+  if (ctx->p.u_mode == 1 && !ctx->uvel) {
+    set_err(&ctx->err, "u_mode = 1 but no velocity field set (lbm_set_velocity)");
+    return LBM_ESTATE;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_objective(lbm_ctx *ctx, const double *H_target_dev, void *lambda_dev, void *dJdQ_dev, double *J) {
+  CTX_CHECK(ctx);
+  if (!H_target_dev || !lambda_dev || !dJdQ_dev) {
+    set_err(&ctx->err, "H_target, lambda and dJdQ must not be NULL");
+    return LBM_EINVAL;
+  }
+  if (lbm_status st = need_adjoint(ctx)) return st;
+  if (lbm_status st = need_ready(ctx)) return st;
+  if (lbm_status st = activate(ctx)) return st;
+  double *H = reinterpret_cast<double *>(ctx->ws + ctx->L.off_H);
+  double *sq = reinterpret_cast<double *>(ctx->ws + ctx->L.off_qx);
+  double *res = reinterpret_cast<double *>(ctx->ws + ctx->L.off_res);
+  KArgs a = make_args(ctx, ctx->cur);
+  a.out2 = H;
+  if (lbm_status st = run_pass(ctx, MODE_MACRO, a)) return st;
+  HIP_TRY(ctx, launch_seed(ctx->Q, ctx->p.storage == LBM_FP64, H, H_target_dev, ctx->n, lambda_dev, dJdQ_dev, sq,
+                           ctx->stream), "seed kernel launch");
+  HIP_TRY(ctx, launch_reduce(nullptr, sq, nullptr, ctx->n, ctx->p.nx, ctx->p.ny, ctx->p.nz, nullptr, 0, nullptr,
+                             nullptr, 0, 0, reinterpret_cast<double *>(ctx->ws + ctx->L.off_part), kPartials, res,
+                             ctx->stream), "reduction launch");
+  double host[3];
+  HIP_TRY(ctx, hipMemcpyAsync(host, res, sizeof(host), hipMemcpyDeviceToHost, ctx->stream), "copy objective");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "objective");
+  if (J) *J = 0.5 * host[1];
+  return LBM_OK;
+}
+
+lbm_status lbm_adjoint_step(lbm_ctx *ctx, const void *lambda_next_dev, void *lambda_prev_dev, void *dJdQ_dev) {
+  CTX_CHECK(ctx);
+  if (!lambda_next_dev || !lambda_prev_dev || lambda_next_dev == lambda_prev_dev) {
+    set_err(&ctx->err, "lambda_next and lambda_prev must be distinct non-NULL buffers");
+    return LBM_EINVAL;
+  }
+  if (lbm_status st = need_adjoint(ctx)) return st;
+  if (lbm_status st = activate(ctx)) return st;
+  KArgs a = make_args(ctx, ctx->cur);
+  HIP_TRY(ctx, launch_adjoint(ctx->Q, ctx->p.storage == LBM_FP64, a, lambda_next_dev, lambda_prev_dev, dJdQ_dev,
+                              ctx->stream), "adjoint kernel launch");
   return LBM_OK;
 }
 

@@ -211,11 +211,14 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
   return b < per * 8 ? (b % 8) * per + b / 8 : b;
 }
 
-template <int Q, int ST, bool NS, bool GEOM, int MODE>
+template <int Q, int ST, bool NS, bool GEOM, int MODE, bool BITS = false>
 __device__ __forceinline__ void bulk_node(const KArgs &a, int64_t m) {
   using R = typename StT<ST>::R;
   if (m >= a.n) return;
-  if constexpr (GEOM) {
+  if constexpr (BITS) {
+    // step kernel: solid and boundary nodes are skipped (1 bit per node)
+    if ((a.skip[m >> 5] >> (m & 31)) & 1u) return;
+  } else if constexpr (GEOM) {
     const uint8_t c = a.cls[m];
     if (c == CLS_SPECIAL) return;
     if (c == CLS_SOLID) {
@@ -364,7 +367,55 @@ __global__ void __launch_bounds__(256) k_fused(const KArgs a, int sblocks) {
     return;
   }
   const int64_t tile = xcd_tile(blockIdx.x - sblocks, gridDim.x - sblocks);
-  bulk_node<Q, ST, NS, true, MODE_STEP>(a, tile * 256 + threadIdx.x);
+  bulk_node<Q, ST, NS, true, MODE_STEP, true>(a, tile * 256 + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Discrete adjoint of the advection-diffusion step (no geometry): node y
+// gathers lam_next_i(y + e_i) (transpose of the pull), applies the transposed
+// collision of node y and writes lam_prev(y); dJdQ(y) += b^T lam.
+// ---------------------------------------------------------------------------
+template <int Q, class R>
+__global__ void __launch_bounds__(256) k_adjoint(const KArgs a, const R *lam_next, R *lam_prev, double *dJdQ) {
+  constexpr int D = Lat<Q>::D;
+  const int64_t m = xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (m >= a.n) return;
+  const int x = (int)(m % a.nx);
+  const int64_t r = m / a.nx;
+  const int y = (int)(r % a.ny);
+  const int z = (int)(r / a.ny);
+  // destination coordinate of a population moving with component c: x + c
+  const int xd[3] = {x == 0 ? a.nx - 1 : x - 1, x, x + 1 == a.nx ? 0 : x + 1};
+  const int yd[3] = {y == 0 ? a.ny - 1 : y - 1, y, y + 1 == a.ny ? 0 : y + 1};
+  const int zd[3] = {z == 0 ? a.nz - 1 : z - 1, z, z + 1 == a.nz ? 0 : z + 1};
+  R g[Q];
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    const int64_t d = xd[Lat<Q>::ex(i) + 1] +
+                      (int64_t)a.nx * (yd[Lat<Q>::ey(i) + 1] + (int64_t)a.ny * zd[Lat<Q>::ez(i) + 1]);
+    g[Lat<Q>::slot(i)] = __builtin_nontemporal_load(lam_next + (int64_t)i * a.n + d);
+  }
+  R ux, uy, uz;
+  prescribed_u<Q, R>(a, m, ux, uy, uz);
+  const R dq = collide_adjoint<D, R>(g, rates<R>(a, false), ux, uy, uz);
+#pragma unroll
+  for (int i = 0; i < Q; i++) __builtin_nontemporal_store(g[Lat<Q>::slot(i)], lam_prev + (int64_t)i * a.n + m);
+  if (dJdQ) dJdQ[m] += double(dq);
+}
+
+// Objective J = 1/2 sum (H - H*)^2 on the canonical state: H from a macro
+// pass (FP64 scratch).  Seeds lam = dJ/dpre (every direction H - H*), sets
+// dJdQ = (H - H*)/2 (Q enters H as Q/2) and leaves (H - H*)^2 in sq.
+template <int Q, class R>
+__global__ void __launch_bounds__(256) k_seed(const double *H, const double *Ht, int64_t n, R *lam, double *dJdQ,
+                                              double *sq) {
+  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (m >= n) return;
+  const double d = H[m] - Ht[m];
+#pragma unroll
+  for (int i = 0; i < Q; i++) lam[(int64_t)i * n + m] = R(d);
+  dJdQ[m] = 0.5 * d;
+  sq[m] = d * d;
 }
 
 // ---------------------------------------------------------------------------
@@ -624,6 +675,35 @@ hipError_t launch_convert(int Q, int storage, bool to_storage, const void *from,
   if (Q == 9) LBM_DISPATCH_ST(storage, (convert_t<9, ST>(to_storage, from, to, n, ref, cls, s)))
   if (Q == 27) LBM_DISPATCH_ST(storage, (convert_t<27, ST>(to_storage, from, to, n, ref, cls, s)))
   return hipErrorInvalidValue;
+}
+
+template <int Q, class R>
+static hipError_t adjoint_t(const KArgs &a, const void *ln, void *lp, void *dq, hipStream_t s) {
+  k_adjoint<Q, R><<<blocks_for(a.n, 256), 256, 0, s>>>(a, static_cast<const R *>(ln), static_cast<R *>(lp),
+                                                         static_cast<double *>(dq));
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(int Q, bool fp64, const KArgs &a, const void *lam_next, void *lam_prev, void *dJdQ,
+                          hipStream_t s) {
+  if (Q == 9) return fp64 ? adjoint_t<9, double>(a, lam_next, lam_prev, dJdQ, s)
+                          : adjoint_t<9, float>(a, lam_next, lam_prev, dJdQ, s);
+  if (Q == 27) return fp64 ? adjoint_t<27, double>(a, lam_next, lam_prev, dJdQ, s)
+                           : adjoint_t<27, float>(a, lam_next, lam_prev, dJdQ, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_seed(int Q, bool fp64, const double *H, const double *Ht, int64_t n, void *lam, void *dJdQ,
+                       double *sq, hipStream_t s) {
+  const unsigned g = blocks_for(n, 256);
+  if (Q == 9) {
+    if (fp64) k_seed<9, double><<<g, 256, 0, s>>>(H, Ht, n, static_cast<double *>(lam), static_cast<double *>(dJdQ), sq);
+    else k_seed<9, float><<<g, 256, 0, s>>>(H, Ht, n, static_cast<float *>(lam), static_cast<double *>(dJdQ), sq);
+  } else {
+    if (fp64) k_seed<27, double><<<g, 256, 0, s>>>(H, Ht, n, static_cast<double *>(lam), static_cast<double *>(dJdQ), sq);
+    else k_seed<27, float><<<g, 256, 0, s>>>(H, Ht, n, static_cast<float *>(lam), static_cast<double *>(dJdQ), sq);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const double *rho, const double *H, const double *qx, int64_t n, int nx,

@@ -56,6 +56,7 @@ struct KArgs {
   const void *hsrc;
   void *hdst;
   const uint8_t *cls;      // node classes, or null when there is no geometry
+  const uint32_t *skip;    // bit m set: node m is not a bulk node (step kernel)
   const void *uvel;        // [3][n] arithmetic type, or null
   const void *src;         // [n] arithmetic type, or null
   const DevLink *links;
@@ -104,6 +105,9 @@ hipError_t launch_reduce(const double *rho, const double *H, const double *qx, i
                          int ny, int nz, const int32_t *cols, int ncols, const double *link_flux,
                          const DevLink *links, int64_t nlinks, int group, double *partials,
                          int npartials, double *out, hipStream_t s);
-hipError_t launch_copy(const void *src, void *dst, int64_t nbytes, hipStream_t s);
+hipError_t launch_adjoint(int Q, bool fp64, const KArgs &a, const void *lam_next, void *lam_prev, void *dJdQ,
+                          hipStream_t s);
+hipError_t launch_seed(int Q, bool fp64, const double *H, const double *Ht, int64_t n, void *lam, void *dJdQ,
+                       double *sq, hipStream_t s);
 
 }  // namespace lbm

@@ -84,6 +84,8 @@ _sig = {
     "lbm_load_state": (C.c_int, [_vp, _vp]),
     "lbm_time": (C.c_int64, [_vp]),
     "lbm_sync": (C.c_int, [_vp]),
+    "lbm_objective": (C.c_int, [_vp, _vp, _vp, _vp, _P(C.c_double)]),
+    "lbm_adjoint_step": (C.c_int, [_vp, _vp, _vp, _vp]),
     "lbm_profile_begin": (C.c_int, [_vp, C.c_int32]),
     "lbm_profile_end": (C.c_int, [_vp, _P(C.c_double), _P(C.c_double), _P(C.c_int64)]),
 }
@@ -234,7 +236,7 @@ class LBM:
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
-        if ctx:
+        if ctx and _lib is not None:
             _lib.lbm_destroy(ctx)
             self.ctx = None
 
@@ -338,6 +340,23 @@ class LBM:
         k = C.c_int64()
         self._ck(_lib.lbm_profile_end(self.ctx, C.byref(b), C.byref(s), C.byref(k)))
         return b.value, s.value, int(k.value)
+
+    # -- discrete adjoint (advection-only, periodic) ------------------------------
+    def objective(self, H_target):
+        """(J, lam, dJdQ): J = 1/2 sum (H - H*)^2 of the canonical state, the adjoint
+        seed lam [Q, n] (arithmetic dtype) and the direct part of dJ/dQ (FP64)."""
+        torch = self.torch
+        Ht = self._dev(H_target, torch.float64).reshape(self.n)
+        lam = torch.empty(self.Q, self.n, dtype=self.rdtype, device=self.device)
+        dq = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        J = C.c_double()
+        self._ck(_lib.lbm_objective(self.ctx, Ht.data_ptr(), lam.data_ptr(), dq.data_ptr(), C.byref(J)))
+        return J.value, lam, dq
+
+    def adjoint_step(self, lam_next, lam_prev, dJdQ=None):
+        """One reverse step into lam_prev; dJdQ (if given) accumulates."""
+        self._ck(_lib.lbm_adjoint_step(self.ctx, lam_next.data_ptr(), lam_prev.data_ptr(),
+                                       None if dJdQ is None else dJdQ.data_ptr()))
 
     def state_bytes(self):
         return int(_lib.lbm_state_bytes(self.ctx))

@@ -1,0 +1,80 @@
+"""Pins of the oracle's discrete adjoint (advection-diffusion with a source).
+
+The adjoint is not in the paper; it is defined as the exact transpose of the
+forward step.  The forward step is affine in (state, Q), so the checks are
+exact identities up to rounding: the transpose identity against the oracle's
+own forward step, and central finite differences of the objective (quadratic
+in Q, so the central difference has no truncation error)."""
+import numpy as np
+import pytest
+
+from paper_2203_01316_amd import workloads as W
+
+
+def _sim(oracle, L=10, Q=9, u=(0.03, -0.02, 0.0), src=None, kind="trt", k=0.02):
+    n = L * L if Q == 9 else L ** 3
+    dims = (L, L, 1) if Q == 9 else (L, L, L)
+    return oracle.Sim(Q, *dims, s_h=oracle.preset(Q, kind, oracle.s_main(k)), u0=u,
+                      src=np.zeros(n) if src is None else src), n
+
+
+def _forward_pre(sim, pre, src):
+    """F(pre; Q) = stream(collide(pre)) with source Q."""
+    sim.set_source(src)
+    fz = np.zeros_like(pre)
+    _, post = sim.collide(fz, pre)
+    sim.set_post(h=post)
+    return sim.pre()[1]
+
+
+@pytest.mark.parametrize("Q,kind", [(9, "trt"), (9, "srt"), (27, "trt")])
+def test_adjoint_is_transpose_of_forward(oracle, Q, kind):
+    L = 8 if Q == 9 else 4
+    sim, n = _sim(oracle, L, Q, kind=kind)
+    rng = np.random.default_rng(40)
+    p = rng.uniform(0.0, 0.3, (Q, n))
+    d = rng.standard_normal((Q, n))
+    src = 0.01 * rng.standard_normal(n)
+    dq = rng.standard_normal(n)
+    lam = rng.standard_normal((Q, n))
+    sim.set_source(src)
+    dJdQ = np.zeros(n)
+    adj = sim.adjoint_step(lam, dJdQ)
+    F0 = _forward_pre(sim, p, src)
+    F1 = _forward_pre(sim, p + d, src)
+    F2 = _forward_pre(sim, p, src + dq)
+    lhs = float((lam * (F1 - F0)).sum())
+    assert lhs == pytest.approx(float((adj * d).sum()), rel=1e-11)
+    lhs = float((lam * (F2 - F0)).sum())
+    assert lhs == pytest.approx(float((dJdQ * dq).sum()), rel=1e-10)
+
+
+def test_adjoint_gradient_matches_central_differences(oracle):
+    L, T = 8, 25
+    rng = np.random.default_rng(41)
+    src = 0.01 * rng.standard_normal(L * L)
+    target = 1.0 + 0.01 * rng.standard_normal(L * L)
+    H0 = W.gaussian_hill(L, 2.0, 0.2, None, (0.0, 0.0), 0.0, 0.0)
+
+    def run(q):
+        sim, _ = _sim(oracle, L, src=q)
+        sim.init(H0)
+        return sim
+
+    sim = run(src)
+    J, g = sim.gradient_source(target, T)
+    eps = 1e-3
+    for node in rng.integers(0, L * L, 6):
+        qp = src.copy()
+        qp[node] += eps
+        qm = src.copy()
+        qm[node] -= eps
+        sp = run(qp)
+        sp.step(T)
+        sm = run(qm)
+        sm.step(T)
+        Jp, _, _ = sp.objective(target)
+        Jm, _, _ = sm.objective(target)
+        fd = (Jp - Jm) / (2 * eps)
+        assert fd == pytest.approx(g[node], rel=1e-7, abs=1e-12)
+    assert J > 0
