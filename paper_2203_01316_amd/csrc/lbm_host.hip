@@ -53,7 +53,7 @@ struct Layout {
   size_t pop_bytes;  // one copy of one lattice
   size_t off_pop[2][2];
   size_t off_cls, off_skip, off_links, off_special, off_groups, off_rho, off_H, off_qx, off_flux, off_part,
-      off_res, off_cols;
+      off_res, off_cols, off_side_f, off_side_h, off_side_u;
   size_t total;
 };
 
@@ -90,8 +90,8 @@ bool validate(const lbm_params *p, std::string *err) {
   if ((int64_t)p->nx * p->ny * p->nz > (int64_t)1 << 31)
     return set_err(err, "too many nodes (%lld), limit 2^31", (long long)node_count(p));
   if (storage_size(p->storage) == 0) return set_err(err, "unknown storage %d", p->storage);
-  if (p->stream != LBM_STREAM_AB)
-    return set_err(err, "stream mode %d not supported (only LBM_STREAM_AB)", p->stream);
+  if (p->stream != LBM_STREAM_AB && p->stream != LBM_STREAM_AA)
+    return set_err(err, "unknown stream mode %d", p->stream);
   if (p->with_ns != 0 && p->with_ns != 1) return set_err(err, "with_ns must be 0 or 1");
   if (p->relax_h < LBM_CM_SRT || p->relax_h > LBM_CM_CUSTOM) return set_err(err, "unknown relax_h %d", p->relax_h);
   if (p->with_ns && (p->relax_f < LBM_CM_SRT || p->relax_f > LBM_CM_CUSTOM))
@@ -139,10 +139,11 @@ Layout layout(const lbm_params *p) {
   const int Q = p->lattice;
   size_t off = 0;
   L.pop_bytes = align_up((size_t)Q * n * storage_size(p->storage));
+  const int copies = p->stream == LBM_STREAM_AA ? 1 : 2;
   for (int lat = 0; lat < 2; lat++)
     for (int c = 0; c < 2; c++) {
-      const bool used = (lat == 1 || p->with_ns);
-      L.off_pop[lat][c] = off;
+      const bool used = (lat == 1 || p->with_ns) && c < copies;
+      L.off_pop[lat][c] = used ? off : L.off_pop[lat][0];
       if (used) off += L.pop_bytes;
     }
   L.off_cls = off;
@@ -169,6 +170,15 @@ Layout layout(const lbm_params *p) {
   off += align_up(sizeof(double) * (3 + kMaxColumns));
   L.off_cols = off;
   off += align_up(sizeof(int32_t) * kMaxColumns);
+  // AA side buffers (arithmetic type): per link f and h, 2 x 3 per boundary node
+  const size_t rsz = p->storage == LBM_FP64 ? 8 : 4;
+  const bool aa = p->stream == LBM_STREAM_AA;
+  L.off_side_f = off;
+  off += aa ? align_up(rsz * (size_t)p->max_links) : 0;
+  L.off_side_h = off;
+  off += aa ? align_up(rsz * (size_t)p->max_links) : 0;
+  L.off_side_u = off;
+  off += aa ? align_up(rsz * 6 * (size_t)p->max_special) : 0;
   L.total = off;
   return L;
 }
@@ -199,6 +209,7 @@ template <int Q>
 bool build_geometry_q(const lbm_params *p, const uint16_t *flags, const double *q, int n_groups,
                       bool want_links, Geometry *G, int64_t *nlinks, int64_t *nspecial, std::string *err) {
   const int64_t N = node_count(p);
+  const bool aa = p->stream == LBM_STREAM_AA;
   int64_t cl = 0, cs = 0;
   if (flags) {
     for (int64_t n = 0; n < N; n++) {
@@ -263,6 +274,30 @@ bool build_geometry_q(const lbm_params *p, const uint16_t *flags, const double *
       cs++;
     }
   }
+  if (aa && flags) {
+    // AA: an outlet node's thread also updates its upstream node, which then
+    // needs no record of its own (see lbm_impl.hpp)
+    std::vector<char> absorbed(want_links ? (size_t)N : 0, 0);
+    for (int64_t n = 0; n < N; n++) {
+      if (ntype(flags, n) != LBM_NODE_OUTLET) continue;
+      const int64_t x = n % p->nx;
+      const int64_t up = x == 0 ? n + p->nx - 1 : n - 1;
+      if (ntype(flags, up) != LBM_NODE_FLUID)
+        return set_err(err, "AA layout: outlet node %lld needs a FLUID upstream node (node %lld)", (long long)n,
+                       (long long)up);
+      if (want_links) {
+        absorbed[up] = 1;
+        G->cls[up] = CLS_SPECIAL;
+      }
+    }
+    if (want_links) {
+      std::vector<DevSpecial> kept;
+      for (const auto &sp : G->special)
+        if (!absorbed[sp.node]) kept.push_back(sp);
+      cs = (int64_t)kept.size();
+      G->special.swap(kept);
+    }
+  }
   if (want_links) {
     // upstream link ranges of outlet nodes (links are sorted by node)
     for (auto &s : G->special) {
@@ -301,7 +336,8 @@ struct lbm_ctx {
   int device;
   char *ws;
   Layout L;
-  int cur;  // copy holding the stored state
+  int cur;    // AB: copy holding the stored state
+  int phase;  // AA: 0 swapped layout (next step pulls and pushes), 1 streamed layout
   bool initialized;
   bool geom;
   int64_t nlinks, nspecial;
@@ -318,9 +354,11 @@ struct lbm_ctx {
   int64_t ev_used = 0;
   bool profiling = false;
   struct {
-    int64_t magic, t, Q, n, storage, with_ns, bytes, pad;
+    int64_t magic, t, Q, n, storage, with_ns, bytes, phase;
   } hdr;
   void *pop(int lat, int c) { return ws + L.off_pop[lat][c]; }
+  bool aa() const { return p.stream == LBM_STREAM_AA; }
+  int lay() const { return !aa() ? LAY_AB : (phase == 0 ? LAY_AA_S : LAY_AA_N); }
 };
 
 #define CTX_CHECK(ctx)                                                        \
@@ -353,10 +391,14 @@ static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   KArgs a;
   memset(&a, 0, sizeof(a));
   const bool ns = ctx->p.with_ns;
+  const int dst_copy = ctx->aa() ? src_copy : src_copy ^ 1;  // AA updates in place
   a.fsrc = ns ? ctx->pop(0, src_copy) : nullptr;
-  a.fdst = ns ? ctx->pop(0, src_copy ^ 1) : nullptr;
+  a.fdst = ns ? ctx->pop(0, dst_copy) : nullptr;
   a.hsrc = ctx->pop(1, src_copy);
-  a.hdst = ctx->pop(1, src_copy ^ 1);
+  a.hdst = ctx->pop(1, dst_copy);
+  a.side_f = ctx->ws + ctx->L.off_side_f;
+  a.side_h = ctx->ws + ctx->L.off_side_h;
+  a.side_u = ctx->ws + ctx->L.off_side_u;
   a.cls = ctx->geom ? reinterpret_cast<const uint8_t *>(ctx->ws + ctx->L.off_cls) : nullptr;
   a.skip = ctx->geom ? reinterpret_cast<const uint32_t *>(ctx->ws + ctx->L.off_skip) : nullptr;
   a.uvel = ctx->uvel;
@@ -370,6 +412,9 @@ static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   a.nx = ctx->p.nx;
   a.ny = ctx->p.ny;
   a.nz = ctx->p.nz;
+  // measured on MI355X: slab-per-XCD order for D2Q9, row order for D3Q27
+  a.tilemap = ctx->Q == 9 ? 0 : 1;
+  a.row_blocks = (ctx->p.nx + 255) / 256;
   for (int k = 0; k < 27; k++) {
     a.sf[k] = ctx->sfc[k];
     a.sh[k] = ctx->shc[k];
@@ -388,7 +433,8 @@ static lbm_status run_pass(lbm_ctx *ctx, int mode, const KArgs &a) {
   if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[ctx->ev_used], ctx->stream), "event record");
   if (mode == MODE_STEP && ctx->geom && ctx->Q == 9) {
     // bulk and boundary nodes in one launch; the boundary time is inside it
-    HIP_TRY(ctx, launch_fused(ctx->p.storage, ctx->p.with_ns, a, ctx->stream), "step kernel launch");
+    HIP_TRY(ctx, launch_fused(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->lay(), a, ctx->stream),
+            "step kernel launch");
     if (timed) {
       HIP_TRY(ctx, hipEventRecord(ctx->ev[ctx->ev_used + 1], ctx->stream), "event record");
       HIP_TRY(ctx, hipEventRecord(ctx->ev[ctx->ev_used + 2], ctx->stream), "event record");
@@ -396,16 +442,24 @@ static lbm_status run_pass(lbm_ctx *ctx, int mode, const KArgs &a) {
     }
     return LBM_OK;
   }
-  HIP_TRY(ctx, launch_pass(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->geom, mode, a, ctx->stream),
+  HIP_TRY(ctx, launch_pass(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->geom, ctx->lay(), mode, a, ctx->stream),
           "bulk kernel launch");
   if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[ctx->ev_used + 1], ctx->stream), "event record");
   if (ctx->geom)
-    HIP_TRY(ctx, launch_special(ctx->Q, ctx->p.storage, ctx->p.with_ns, mode, a, ctx->stream),
+    HIP_TRY(ctx, launch_special(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->lay(), mode, a, ctx->stream),
             "boundary kernel launch");
   if (timed) {
     HIP_TRY(ctx, hipEventRecord(ctx->ev[ctx->ev_used + 2], ctx->stream), "event record");
     ctx->ev_used += 3;
   }
+  return LBM_OK;
+}
+
+// AA: side buffers of the boundary nodes from the stored state.
+static lbm_status rebuild_side(lbm_ctx *ctx) {
+  if (!ctx->aa() || !ctx->geom || ctx->nspecial == 0) return LBM_OK;
+  KArgs a = make_args(ctx, 0);
+  HIP_TRY(ctx, launch_side(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->lay(), a, ctx->stream), "side kernel launch");
   return LBM_OK;
 }
 
@@ -500,6 +554,7 @@ lbm_status lbm_create(const lbm_params *p, void *workspace_dev, void *hip_stream
   ctx->ws = static_cast<char *>(workspace_dev);
   ctx->L = layout(p);
   ctx->cur = 0;
+  ctx->phase = 0;
   ctx->initialized = false;
   ctx->geom = false;
   ctx->nlinks = ctx->nspecial = 0;
@@ -574,6 +629,7 @@ lbm_status lbm_set_geometry(lbm_ctx *ctx, const uint16_t *flags, const double *q
   ctx->nlinks = nl;
   ctx->nspecial = ns;
   ctx->host_links = std::move(G.links);
+  if (ctx->initialized) return rebuild_side(ctx);
   return LBM_OK;
 }
 
@@ -615,6 +671,7 @@ lbm_status lbm_init_equilibrium(lbm_ctx *ctx, const double *rho_dev, const doubl
   InitArgs a;
   memset(&a, 0, sizeof(a));
   ctx->cur = 0;
+  ctx->phase = 0;
   a.fdst = ctx->p.with_ns ? ctx->pop(0, 0) : nullptr;
   a.hdst = ctx->pop(1, 0);
   a.rho = rho_dev;
@@ -633,10 +690,11 @@ lbm_status lbm_init_equilibrium(lbm_ctx *ctx, const double *rho_dev, const doubl
   const bool dev = ctx->p.storage == LBM_FP32_DEV || ctx->p.storage == LBM_FP16_DEV;
   a.fref = dev ? ctx->p.rho_ref : 0.0;
   a.href = dev ? ctx->p.H_ref : 0.0;
-  HIP_TRY(ctx, launch_init(ctx->Q, ctx->p.storage, ctx->p.with_ns, a, ctx->stream), "init kernel launch");
+  HIP_TRY(ctx, launch_init(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->lay(), a, ctx->stream),
+          "init kernel launch");
   ctx->t = 0;
   ctx->initialized = true;
-  return LBM_OK;
+  return rebuild_side(ctx);
 }
 
 lbm_status lbm_step(lbm_ctx *ctx, int32_t nsteps) {
@@ -650,7 +708,10 @@ lbm_status lbm_step(lbm_ctx *ctx, int32_t nsteps) {
   for (int s = 0; s < nsteps; s++) {
     KArgs a = make_args(ctx, ctx->cur);
     if (lbm_status st = run_pass(ctx, MODE_STEP, a)) return st;
-    ctx->cur ^= 1;
+    if (ctx->aa())
+      ctx->phase ^= 1;
+    else
+      ctx->cur ^= 1;
     ctx->t++;
   }
   return LBM_OK;
@@ -688,9 +749,9 @@ lbm_status lbm_get_populations(lbm_ctx *ctx, int32_t lattice, int32_t which, dou
   const bool dev = ctx->p.storage == LBM_FP32_DEV || ctx->p.storage == LBM_FP16_DEV;
   if (which == 1) {
     const double ref = dev ? (lattice == 0 ? ctx->p.rho_ref : ctx->p.H_ref) : 0.0;
-    const uint8_t *cls = ctx->geom ? reinterpret_cast<const uint8_t *>(ctx->ws + ctx->L.off_cls) : nullptr;
-    HIP_TRY(ctx, launch_convert(ctx->Q, ctx->p.storage, false, ctx->pop(lattice, ctx->cur), dst_dev, ctx->n, ref,
-                                cls, ctx->stream), "convert kernel launch");
+    KArgs a = make_args(ctx, ctx->cur);
+    HIP_TRY(ctx, launch_convert(ctx->Q, ctx->p.storage, ctx->lay(), false, a, ctx->pop(lattice, ctx->cur), dst_dev,
+                                ref, ctx->stream), "convert kernel launch");
     return LBM_OK;
   }
   KArgs a = make_args(ctx, ctx->cur);
@@ -708,11 +769,13 @@ lbm_status lbm_set_populations(lbm_ctx *ctx, int32_t lattice, const double *src_
   if (lbm_status st = activate(ctx)) return st;
   const bool dev = ctx->p.storage == LBM_FP32_DEV || ctx->p.storage == LBM_FP16_DEV;
   const double ref = dev ? (lattice == 0 ? ctx->p.rho_ref : ctx->p.H_ref) : 0.0;
-  HIP_TRY(ctx, launch_convert(ctx->Q, ctx->p.storage, true, src_dev, ctx->pop(lattice, ctx->cur), ctx->n, ref,
-                              nullptr, ctx->stream), "convert kernel launch");
+  KArgs a = make_args(ctx, ctx->cur);
+  a.cls = nullptr;
+  HIP_TRY(ctx, launch_convert(ctx->Q, ctx->p.storage, ctx->lay(), true, a, src_dev, ctx->pop(lattice, ctx->cur), ref,
+                              ctx->stream), "convert kernel launch");
   ctx->t = t;
   ctx->initialized = true;
-  return LBM_OK;
+  return rebuild_side(ctx);
 }
 
 lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32_t n_columns, double *out,
@@ -837,9 +900,10 @@ lbm_status lbm_save_state(lbm_ctx *ctx, void *dst_dev) {
   ctx->hdr.t = ctx->t;
   ctx->hdr.Q = ctx->Q;
   ctx->hdr.n = ctx->n;
-  ctx->hdr.storage = ctx->p.storage;
+  ctx->hdr.storage = ctx->p.storage | (ctx->p.stream << 8);
   ctx->hdr.with_ns = ctx->p.with_ns;
   ctx->hdr.bytes = (int64_t)lbm_state_bytes(ctx);
+  ctx->hdr.phase = ctx->aa() ? ctx->phase : 0;
   char *d = static_cast<char *>(dst_dev);
   HIP_TRY(ctx, hipMemcpyAsync(d, &ctx->hdr, sizeof(ctx->hdr), hipMemcpyHostToDevice, ctx->stream), "save header");
   size_t off = kAlign;
@@ -862,9 +926,10 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *src_dev) {
   decltype(ctx->hdr) h;
   HIP_TRY(ctx, hipMemcpyAsync(&h, src_dev, sizeof(h), hipMemcpyDeviceToHost, ctx->stream), "load header");
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "load header");
-  if (h.magic != 0x4c424d5354415445LL || h.Q != ctx->Q || h.n != ctx->n || h.storage != ctx->p.storage ||
+  if (h.magic != 0x4c424d5354415445LL || h.Q != ctx->Q || h.n != ctx->n ||
+      h.storage != (ctx->p.storage | (ctx->p.stream << 8)) ||
       h.with_ns != ctx->p.with_ns || h.bytes != (int64_t)lbm_state_bytes(ctx)) {
-    set_err(&ctx->err, "snapshot does not match this context (lattice, size, storage or lattices differ)");
+    set_err(&ctx->err, "snapshot does not match this context (lattice, size, storage, layout or lattices differ)");
     return LBM_EINVAL;
   }
   const char *s = static_cast<const char *>(src_dev);
@@ -875,8 +940,9 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *src_dev) {
     off += ctx->L.pop_bytes;
   }
   ctx->t = h.t;
+  ctx->phase = ctx->aa() ? (int)(h.phase & 1) : 0;
   ctx->initialized = true;
-  return LBM_OK;
+  return rebuild_side(ctx);
 }
 
 int64_t lbm_time(const lbm_ctx *ctx) { return ctx ? ctx->t : -1; }

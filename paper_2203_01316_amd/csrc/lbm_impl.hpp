@@ -1,0 +1,857 @@
+// lbm_impl.hpp -- templated kernels of the fused central-moment
+// stream-and-collide step (gfx950, one node per thread, structure-of-arrays
+// populations).  Included by one translation unit per lattice.
+//
+// Work split per step:
+//   bulk nodes      every node of class CLS_BULK (no cut link, not EQ/OUTLET):
+//                   pull of Q populations per lattice, velocity from f (or
+//                   prescribed), central-moment collision in registers, store.
+//   boundary nodes  one thread per node: pull, wall links (BB/IBB on f,
+//                   ABB/IABB on h), outlet copy, EQ reset, then the same
+//                   collision.
+//
+// Streaming layouts (LAY):
+//   LAY_AB    two arrays: read the post-collision state of step t-1 from the
+//             source array (g*_i at node x in slot i), pull g_i(x) =
+//             g*_i(x - e_i), write g*_i(x) to slot i of node x in the other
+//             array.
+//   LAY_AA_S  one array, "swapped" layout: slot opp(i) of node x holds
+//             g*_i(x).  The step pulls slot opp(i) of x - e_i and pushes the
+//             new g*_i(x) to slot i of x + e_i, which leaves the array in ...
+//   LAY_AA_N  ... the "streamed" layout: slot i of node y holds
+//             g*_i(y - e_i), the pulled value of y.  The step reads its own
+//             slots and writes g*_i(x) to slot opp(i) of x (back to S).
+// In both AA steps every slot a thread reads is written in that step by the
+// same thread only, so the in-place update has no race.  Two inputs of the
+// boundary rules are the exception: the post-collision value g*_opp(i)(x_b)
+// of a boundary node and its velocity at t-1 sit in slots another thread
+// overwrites, so each boundary node keeps them in side buffers (per link and
+// per node) that it reads and rewrites itself.  An outlet node's thread also
+// updates its upstream node, reading both before writing either.
+#pragma once
+
+#include "lbm_device.hpp"
+#include "lbm_kernels.hpp"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// Storage traits
+// ---------------------------------------------------------------------------
+template <int ST>
+struct StT;
+template <>
+struct StT<ST_FP64> {
+  using S = double;
+  using R = double;
+  static constexpr bool DEV = false;
+};
+template <>
+struct StT<ST_FP32> {
+  using S = float;
+  using R = float;
+  static constexpr bool DEV = false;
+};
+template <>
+struct StT<ST_FP32_DEV> {
+  using S = float;
+  using R = float;
+  static constexpr bool DEV = true;
+};
+template <>
+struct StT<ST_FP16_DEV> {
+  using S = __half;
+  using R = float;
+  static constexpr bool DEV = true;
+};
+
+// Load / store population i (stored in slot `slot`) of node m.  The deviation
+// storages keep g_i - w_i g_ref; w_i = w_opp(i), so a swapped slot needs no
+// other weight.
+template <int Q, int ST>
+__device__ __forceinline__ typename StT<ST>::R ldp(const void *base, int slot, int64_t n, int64_t m,
+                                                   typename StT<ST>::R ref) {
+  using T = StT<ST>;
+  using R = typename T::R;
+  const typename T::S *p = static_cast<const typename T::S *>(base) + (int64_t)slot * n + m;
+  R v = StoreT<typename T::S>::ld(p);
+  if constexpr (T::DEV) v += weight<Q, R>(slot) * ref;
+  return v;
+}
+
+template <int Q, int ST>
+__device__ __forceinline__ void stp(void *base, int slot, int64_t n, int64_t m, typename StT<ST>::R v,
+                                    typename StT<ST>::R ref) {
+  using T = StT<ST>;
+  if constexpr (T::DEV) v -= weight<Q, typename T::R>(slot) * ref;
+  typename T::S *p = static_cast<typename T::S *>(base) + (int64_t)slot * n + m;
+  StoreT<typename T::S>::st(p, v);
+}
+
+// Value a store followed by a load of population i would return.
+template <int Q, int ST>
+__device__ __forceinline__ typename StT<ST>::R roundtrip(int i, typename StT<ST>::R v, typename StT<ST>::R ref) {
+  using T = StT<ST>;
+  using R = typename T::R;
+  if constexpr (!T::DEV) {
+    return v;
+  } else {
+    const R d = v - weight<Q, R>(i) * ref;
+    R back;
+    if constexpr (sizeof(typename T::S) == 2)
+      back = __half2float(__float2half_rn(d));
+    else
+      back = d;
+    return back + weight<Q, R>(i) * ref;
+  }
+}
+
+template <class R>
+__device__ __forceinline__ const R *rates(const KArgs &a, bool f);
+template <>
+__device__ __forceinline__ const double *rates<double>(const KArgs &a, bool f) {
+  return f ? a.sf : a.sh;
+}
+template <>
+__device__ __forceinline__ const float *rates<float>(const KArgs &a, bool f) {
+  return f ? a.sf32 : a.sh32;
+}
+
+__device__ __forceinline__ int wrapm(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+struct Node {
+  int x, y, z;
+};
+
+__device__ __forceinline__ Node coords(const KArgs &a, int64_t m) {
+  Node c;
+  c.x = (int)(m % a.nx);
+  const int64_t r = m / a.nx;
+  c.y = (int)(r % a.ny);
+  c.z = (int)(r / a.ny);
+  return c;
+}
+
+// node x + sign * e_i with periodic wrap
+template <int Q>
+__device__ __forceinline__ int64_t shifted(const KArgs &a, Node c, int i, int sign) {
+  const int xs = wrapm(c.x + sign * Lat<Q>::ex(i), a.nx);
+  const int ys = wrapm(c.y + sign * Lat<Q>::ey(i), a.ny);
+  const int zs = wrapm(c.z + sign * Lat<Q>::ez(i), a.nz);
+  return xs + (int64_t)a.nx * (ys + (int64_t)a.ny * zs);
+}
+
+// Prescribed velocity at node m (field or uniform).
+template <int Q, class R>
+__device__ __forceinline__ void prescribed_u(const KArgs &a, int64_t m, R &ux, R &uy, R &uz) {
+  if (a.with_uvel) {
+    const R *u = static_cast<const R *>(a.uvel);
+    ux = u[m];
+    uy = u[a.n + m];
+    uz = Lat<Q>::D == 3 ? u[2 * a.n + m] : R(0);
+  } else {
+    ux = R(a.u0[0]);
+    uy = R(a.u0[1]);
+    uz = Lat<Q>::D == 3 ? R(a.u0[2]) : R(0);
+  }
+}
+
+// rho and velocity of a population set in direction order.
+template <int Q, class R>
+__device__ __forceinline__ void velocity_dir(const R *f, R &rho, R &ux, R &uy, R &uz) {
+  R r = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    r += f[i];
+    if (Lat<Q>::ex(i) > 0) jx += f[i];
+    if (Lat<Q>::ex(i) < 0) jx -= f[i];
+    if (Lat<Q>::ey(i) > 0) jy += f[i];
+    if (Lat<Q>::ey(i) < 0) jy -= f[i];
+    if (Lat<Q>::ez(i) > 0) jz += f[i];
+    if (Lat<Q>::ez(i) < 0) jz -= f[i];
+  }
+  const R inv = R(1) / r;
+  rho = r;
+  ux = jx * inv;
+  uy = jy * inv;
+  uz = Lat<Q>::D == 3 ? jz * inv : R(0);
+}
+
+// ---------------------------------------------------------------------------
+// Layout-dependent addressing
+// ---------------------------------------------------------------------------
+// (slot, node) holding the pulled pre-collision value g_i(x) = g*_i(x - e_i)
+template <int Q, int LAY>
+__device__ __forceinline__ void pull_addr(const KArgs &a, Node c, int64_t m, int i, int &slot, int64_t &node) {
+  if constexpr (LAY == LAY_AA_N) {
+    slot = i;
+    node = m;
+  } else {
+    slot = LAY == LAY_AA_S ? Lat<Q>::opp(i) : i;
+    node = shifted<Q>(a, c, i, -1);
+  }
+}
+
+// (slot, node) receiving the new post-collision value g*_i(x)
+template <int Q, int LAY>
+__device__ __forceinline__ void store_addr(const KArgs &a, Node c, int64_t m, int i, int &slot, int64_t &node) {
+  if constexpr (LAY == LAY_AB) {
+    slot = i;
+    node = m;
+  } else if constexpr (LAY == LAY_AA_S) {
+    slot = i;
+    node = shifted<Q>(a, c, i, +1);
+  } else {
+    slot = Lat<Q>::opp(i);
+    node = m;
+  }
+}
+
+// (slot, node) holding the stored post-collision value g*_i(x) of step t-1
+// (read-only use: output passes, side rebuild, AB boundary rules)
+template <int Q, int LAY>
+__device__ __forceinline__ void post_addr(const KArgs &a, Node c, int64_t m, int i, int &slot, int64_t &node) {
+  if constexpr (LAY == LAY_AB) {
+    slot = i;
+    node = m;
+  } else if constexpr (LAY == LAY_AA_S) {
+    slot = Lat<Q>::opp(i);
+    node = m;
+  } else {
+    slot = i;
+    node = shifted<Q>(a, c, i, +1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Epilogue: pre-collision populations f, h (direction order) of node m ->
+// collide and store (f, h then hold the stored post-collision values), or
+// write them / their moments out.
+// ---------------------------------------------------------------------------
+template <int Q, int ST, bool NS, int MODE, int LAY>
+__device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, typename StT<ST>::R *f,
+                                            typename StT<ST>::R *h) {
+  using R = typename StT<ST>::R;
+  constexpr int D = Lat<Q>::D;
+  R rho = 0, ux, uy, uz;
+  if constexpr (NS)
+    velocity_dir<Q, R>(f, rho, ux, uy, uz);
+  else
+    prescribed_u<Q, R>(a, m, ux, uy, uz);
+  const R src = a.src ? static_cast<const R *>(a.src)[m] : R(0);
+  if constexpr (MODE == MODE_STEP) {
+    R g[Q];
+    if constexpr (NS) {
+#pragma unroll
+      for (int i = 0; i < Q; i++) g[Lat<Q>::slot(i)] = f[i];
+      collide<D, R>(g, rates<R>(a, true), ux, uy, uz, R(0));
+#pragma unroll
+      for (int i = 0; i < Q; i++) {
+        int sl;
+        int64_t nd;
+        store_addr<Q, LAY>(a, c, m, i, sl, nd);
+        f[i] = g[Lat<Q>::slot(i)];
+        stp<Q, ST>(a.fdst, sl, a.n, nd, f[i], R(a.fref));
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < Q; i++) g[Lat<Q>::slot(i)] = h[i];
+    collide<D, R>(g, rates<R>(a, false), ux, uy, uz, src);
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      int sl;
+      int64_t nd;
+      store_addr<Q, LAY>(a, c, m, i, sl, nd);
+      h[i] = g[Lat<Q>::slot(i)];
+      stp<Q, ST>(a.hdst, sl, a.n, nd, h[i], R(a.href));
+    }
+  } else if constexpr (MODE == MODE_PRE) {
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      if constexpr (NS)
+        if (a.out0) a.out0[i * a.n + m] = double(f[i]);
+      if (a.out1) a.out1[i * a.n + m] = double(h[i]);
+    }
+  } else {
+    double H = 0.0, qx = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      H += double(h[i]);
+      qx += double(Lat<Q>::ex(i)) * double(h[i]);
+    }
+    H += 0.5 * double(src);
+    if (a.out0) a.out0[m] = double(rho);
+    if (a.out1) {
+      a.out1[m] = double(ux);
+      a.out1[a.n + m] = double(uy);
+      a.out1[2 * a.n + m] = double(uz);
+    }
+    if (a.out2) a.out2[m] = H;
+    if (a.out3) a.out3[m] = qx;
+  }
+}
+
+// Solid nodes carry no state: the output modes report zeros for them.
+template <int Q, bool NS, int MODE>
+__device__ __forceinline__ void solid_node(const KArgs &a, int64_t m) {
+  if constexpr (MODE == MODE_PRE) {
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      if constexpr (NS)
+        if (a.out0) a.out0[i * a.n + m] = 0.0;
+      if (a.out1) a.out1[i * a.n + m] = 0.0;
+    }
+  } else if constexpr (MODE == MODE_MACRO) {
+    if (a.out0) a.out0[m] = 0.0;
+    if (a.out1) {
+      a.out1[m] = 0.0;
+      a.out1[a.n + m] = 0.0;
+      a.out1[2 * a.n + m] = 0.0;
+    }
+    if (a.out2) a.out2[m] = 0.0;
+    if (a.out3) a.out3[m] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block -> tile order.  Workgroups of one dispatch go round-robin to the 8
+// XCDs (block b runs on XCD b % 8), and each XCD has its own L2.
+//  - one slab per XCD: block b takes tile (b % 8) * per + b / 8, so each XCD
+//    streams through one contiguous eighth of the lattice, and the cache lines
+//    that neighbouring tiles of a row share through the +-1 pull shifts stay in
+//    one L2 (wide 2-D rows span several blocks);
+//  - rows per XCD: the blocks of one x-row stay on one XCD and consecutive rows
+//    go to consecutive XCDs, so all XCDs work on nearby memory (3-D, where a
+//    row is about one block and the slab order spreads the XCDs over distant
+//    DRAM pages).
+// Tail blocks that do not fill a whole round keep their own index.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
+  const int64_t per = nb / 8;
+  return b < per * 8 ? (b % 8) * per + b / 8 : b;
+}
+
+__device__ __forceinline__ int64_t row_tile(int64_t b, int64_t nb, int64_t G) {
+  const int64_t full = nb - nb % (8 * G);
+  if (b >= full) return b;
+  const int64_t x = b % 8, k = b / 8;
+  return ((k / G) * 8 + x) * G + (k % G);
+}
+
+__device__ __forceinline__ int64_t tile_of(const KArgs &a, int64_t b, int64_t nb) {
+  return a.tilemap == 0 ? xcd_tile(b, nb) : row_tile(b, nb, a.row_blocks);
+}
+
+// ---------------------------------------------------------------------------
+// Bulk nodes
+// ---------------------------------------------------------------------------
+template <int Q, int ST, bool NS, bool GEOM, int MODE, int LAY, bool BITS = false>
+__device__ __forceinline__ void bulk_node(const KArgs &a, int64_t m) {
+  using R = typename StT<ST>::R;
+  if (m >= a.n) return;
+  if constexpr (BITS) {
+    // step kernel: solid and boundary nodes are skipped (1 bit per node)
+    if ((a.skip[m >> 5] >> (m & 31)) & 1u) return;
+  } else if constexpr (GEOM) {
+    const uint8_t c = a.cls[m];
+    if (c == CLS_SPECIAL) return;
+    if (c == CLS_SOLID) {
+      solid_node<Q, NS, MODE>(a, m);
+      return;
+    }
+  }
+  const Node c = coords(a, m);
+  R f[Q], h[Q];
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    int sl;
+    int64_t nd;
+    pull_addr<Q, LAY>(a, c, m, i, sl, nd);
+    if constexpr (NS) f[i] = ldp<Q, ST>(a.fsrc, sl, a.n, nd, R(a.fref));
+    h[i] = ldp<Q, ST>(a.hsrc, sl, a.n, nd, R(a.href));
+  }
+  finish_node<Q, ST, NS, MODE, LAY>(a, c, m, f, h);
+}
+
+template <int Q, int ST, bool NS, bool GEOM, int MODE, int LAY>
+__global__ void __launch_bounds__(256) k_bulk(const KArgs a) {
+  const int64_t tile = tile_of(a, blockIdx.x, gridDim.x);
+  bulk_node<Q, ST, NS, GEOM, MODE, LAY>(a, tile * 256 + threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Boundary nodes
+// ---------------------------------------------------------------------------
+// Pulled populations of node m plus the wall links in mask (links stored from
+// lb, one per set bit in increasing direction), direction order.  side_node
+// indexes the node's velocity entry of the AA side buffer.  flux (optional)
+// receives h_opp(x_b, t) - h*_i(x_b, t-1) per link.
+template <int Q, int ST, bool NS, int LAY>
+__device__ __forceinline__ void pull_links(const KArgs &a, int64_t m, int32_t lb, uint32_t mask, int64_t side_node,
+                                           typename StT<ST>::R *f, typename StT<ST>::R *h, double *flux) {
+  using R = typename StT<ST>::R;
+  const Node c = coords(a, m);
+  const R fref = R(a.fref), href = R(a.href);
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    int sl;
+    int64_t nd;
+    pull_addr<Q, LAY>(a, c, m, i, sl, nd);
+    if constexpr (NS) f[i] = ldp<Q, ST>(a.fsrc, sl, a.n, nd, fref);
+    h[i] = ldp<Q, ST>(a.hsrc, sl, a.n, nd, href);
+  }
+  if (mask == 0) return;
+  // velocity of the boundary node for the wall equilibrium: momentum over
+  // density of its post-collision f of step t-1, or the prescribed velocity
+  R ux, uy, uz;
+  if constexpr (NS) {
+    if constexpr (LAY == LAY_AB) {
+      R fb[Q], rho;
+#pragma unroll
+      for (int i = 0; i < Q; i++) fb[i] = ldp<Q, ST>(a.fsrc, i, a.n, m, fref);
+      velocity_dir<Q, R>(fb, rho, ux, uy, uz);
+    } else {
+      const R *su = static_cast<const R *>(a.side_u) + 3 * side_node;
+      ux = su[0];
+      uy = su[1];
+      uz = su[2];
+    }
+  } else {
+    prescribed_u<Q, R>(a, m, ux, uy, uz);
+  }
+#pragma unroll
+  for (int i = 1; i < Q; i++) {
+    if (!((mask >> i) & 1u)) continue;
+    const int o = Lat<Q>::opp(i);
+    const int32_t l = lb + __popc(mask & ((1u << i) - 1u));
+    const DevLink lk = a.links[l];
+    const DevGroup &G = a.groups[lk.group];
+    // g*_i(x_b) of step t-1; g*_o(x_b) is kept in the side buffer in the AA
+    // layouts; g*_i(x_f) is the pulled value f[i] / h[i] (never rewritten by
+    // another link when it is used: that link would need x_f solid)
+    int sl;
+    int64_t nd;
+    post_addr<Q, LAY>(a, c, m, i, sl, nd);
+    if constexpr (NS) {
+      const R gbi = ldp<Q, ST>(a.fsrc, sl, a.n, nd, fref);
+      if (G.f_scheme == 0 || lk.xf_solid || lk.q == 0.5) {
+        f[o] = gbi;  // bounce-back (Eq. IBB at q = 1/2)
+      } else {
+        const R gbo = LAY == LAY_AB ? ldp<Q, ST>(a.fsrc, o, a.n, m, fref) : static_cast<const R *>(a.side_f)[l];
+        f[o] = wall_ibb<R>(R(lk.q), gbi, gbo, f[i]);
+      }
+    }
+    const R hbi = ldp<Q, ST>(a.hsrc, sl, a.n, nd, href);
+    const R geq = geq_dir<Q, R>(i, R(G.H_w), ux, uy, uz);
+    if (G.h_scheme == 0 || lk.xf_solid || lk.q == 0.5) {
+      h[o] = -hbi + R(2) * geq;  // anti-bounce-back (Eq. IABB at q = 1/2)
+    } else {
+      const R hbo = LAY == LAY_AB ? ldp<Q, ST>(a.hsrc, o, a.n, m, href) : static_cast<const R *>(a.side_h)[l];
+      h[o] = wall_iabb<R>(R(lk.q), hbi, hbo, h[i], geq);
+    }
+    if (flux) flux[l] = double(h[o]) - double(hbi);
+  }
+}
+
+// AA side values of one boundary node after its update: g*_opp(i)(x_b) per
+// link and the velocity of the stored f, both as they read back from storage.
+template <int Q, int ST, bool NS>
+__device__ __forceinline__ void save_side(const KArgs &a, int32_t lb, uint32_t mask, int64_t side_node,
+                                          const typename StT<ST>::R *fpost, const typename StT<ST>::R *hpost) {
+  using R = typename StT<ST>::R;
+  if constexpr (NS) {
+    R fr[Q], rho, ux, uy, uz;
+#pragma unroll
+    for (int i = 0; i < Q; i++) fr[i] = roundtrip<Q, ST>(i, fpost[i], R(a.fref));
+    if (mask) {
+      R *su = static_cast<R *>(a.side_u) + 3 * side_node;
+      velocity_dir<Q, R>(fr, rho, ux, uy, uz);
+      su[0] = ux;
+      su[1] = uy;
+      su[2] = uz;
+    }
+#pragma unroll
+    for (int i = 1; i < Q; i++) {
+      if (!((mask >> i) & 1u)) continue;
+      const int32_t l = lb + __popc(mask & ((1u << i) - 1u));
+      static_cast<R *>(a.side_f)[l] = fr[Lat<Q>::opp(i)];
+    }
+  }
+#pragma unroll
+  for (int i = 1; i < Q; i++) {
+    if (!((mask >> i) & 1u)) continue;
+    const int32_t l = lb + __popc(mask & ((1u << i) - 1u));
+    const int o = Lat<Q>::opp(i);
+    static_cast<R *>(a.side_h)[l] = roundtrip<Q, ST>(o, hpost[o], R(a.href));
+  }
+}
+
+template <int Q, int ST, bool NS, int MODE, int LAY>
+__device__ __forceinline__ void special_node(const KArgs &a, int64_t t) {
+  using R = typename StT<ST>::R;
+  constexpr bool AA = LAY != LAY_AB;
+  if (t >= a.nspecial) return;
+  const DevSpecial sp = a.special[t];
+  const int64_t m = sp.node;
+  const Node c = coords(a, m);
+  double *flux = MODE == MODE_MACRO ? a.link_flux : nullptr;
+  R f[Q], h[Q];
+  if (sp.type == NODE_EQ) {
+    if (flux) pull_links<Q, ST, NS, LAY>(a, m, sp.lb, sp.mask, 2 * t, f, h, flux);
+    const DevGroup &G = a.groups[sp.group];
+    R ux, uy, uz;
+    if (NS && !a.with_uvel) {
+      ux = R(G.u_w[0]);
+      uy = R(G.u_w[1]);
+      uz = Lat<Q>::D == 3 ? R(G.u_w[2]) : R(0);
+    } else {
+      prescribed_u<Q, R>(a, m, ux, uy, uz);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      if constexpr (NS) f[i] = geq_dir<Q, R>(i, R(G.rho_w), ux, uy, uz);
+      h[i] = geq_dir<Q, R>(i, R(G.H_w), ux, uy, uz);
+    }
+  } else {
+    pull_links<Q, ST, NS, LAY>(a, m, sp.lb, sp.mask, 2 * t, f, h, flux);
+    if (sp.type == NODE_OUTLET) {
+      const int64_t up = c.x == 0 ? m + a.nx - 1 : m - 1;
+      R fu[Q], hu[Q];
+      // AA: this thread also owns the upstream node (its flux included)
+      pull_links<Q, ST, NS, LAY>(a, up, sp.ub, sp.umask, 2 * t + 1, fu, hu, AA ? flux : nullptr);
+#pragma unroll
+      for (int i = 0; i < Q; i++) {
+        if (Lat<Q>::ex(i) < 0) {
+          if constexpr (NS) f[i] = fu[i];
+          h[i] = hu[i];
+        }
+      }
+      if constexpr (AA) {
+        finish_node<Q, ST, NS, MODE, LAY>(a, coords(a, up), up, fu, hu);
+        if constexpr (MODE == MODE_STEP) save_side<Q, ST, NS>(a, sp.ub, sp.umask, 2 * t + 1, fu, hu);
+      }
+    }
+  }
+  finish_node<Q, ST, NS, MODE, LAY>(a, c, m, f, h);
+  if constexpr (AA && MODE == MODE_STEP) save_side<Q, ST, NS>(a, sp.lb, sp.mask, 2 * t, f, h);
+}
+
+template <int Q, int ST, bool NS, int MODE, int LAY>
+__global__ void __launch_bounds__(64) k_special(const KArgs a) {
+  special_node<Q, ST, NS, MODE, LAY>(a, (int64_t)blockIdx.x * 64 + threadIdx.x);
+}
+
+// One launch per step with geometry (D2Q9): the first `sblocks` blocks (a
+// multiple of 8, so the XCD of a bulk block is unchanged) take the boundary
+// nodes, whose long chains of dependent loads then overlap the bulk stream
+// instead of running after it.
+template <int Q, int ST, bool NS, int LAY>
+__global__ void __launch_bounds__(256) k_fused(const KArgs a, int sblocks) {
+  if ((int)blockIdx.x < sblocks) {
+    special_node<Q, ST, NS, MODE_STEP, LAY>(a, (int64_t)blockIdx.x * 256 + threadIdx.x);
+    return;
+  }
+  const int64_t tile = tile_of(a, blockIdx.x - sblocks, gridDim.x - sblocks);
+  bulk_node<Q, ST, NS, true, MODE_STEP, LAY, true>(a, tile * 256 + threadIdx.x);
+}
+
+// AA side buffers from the stored state (after init, set or load).
+template <int Q, int ST, bool NS, int LAY>
+__global__ void __launch_bounds__(64) k_side(const KArgs a) {
+  using R = typename StT<ST>::R;
+  const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (t >= a.nspecial) return;
+  const DevSpecial sp = a.special[t];
+  for (int k = 0; k < 2; k++) {
+    if (k == 1 && sp.type != NODE_OUTLET) break;
+    const int64_t m = k == 0 ? sp.node : (sp.node % a.nx == 0 ? sp.node + a.nx - 1 : sp.node - 1);
+    const Node c = coords(a, m);
+    R f[Q], h[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      int sl;
+      int64_t nd;
+      post_addr<Q, LAY>(a, c, m, i, sl, nd);
+      if constexpr (NS) f[i] = ldp<Q, ST>(a.fsrc, sl, a.n, nd, R(a.fref));
+      else f[i] = R(0);
+      h[i] = ldp<Q, ST>(a.hsrc, sl, a.n, nd, R(a.href));
+    }
+    save_side<Q, ST, NS>(a, k == 0 ? sp.lb : sp.ub, k == 0 ? sp.mask : sp.umask, 2 * t + k, f, h);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initial state: g*_i(x) = g^eq_i(fields at x + e_i) in FP64, stored at the
+// post-collision address of the layout (AB, or the swapped AA layout).
+// ---------------------------------------------------------------------------
+template <int Q, int ST, bool NS, int LAY>
+__global__ void __launch_bounds__(256) k_init(const InitArgs a) {
+  using R = typename StT<ST>::R;
+  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (m >= a.n) return;
+  const int x = (int)(m % a.nx);
+  const int64_t r = m / a.nx;
+  const int y = (int)(r % a.ny);
+  const int z = (int)(r / a.ny);
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    const int xs = wrapm(x + Lat<Q>::ex(i), a.nx);
+    const int ys = wrapm(y + Lat<Q>::ey(i), a.ny);
+    const int zs = wrapm(z + Lat<Q>::ez(i), a.nz);
+    const int64_t s = xs + (int64_t)a.nx * (ys + (int64_t)a.ny * zs);
+    double ux, uy, uz;
+    if (a.u) {
+      ux = a.u[s];
+      uy = a.u[a.n + s];
+      uz = a.u[2 * a.n + s];
+    } else if (a.uvel) {
+      const R *u = static_cast<const R *>(a.uvel);
+      ux = double(u[s]);
+      uy = double(u[a.n + s]);
+      uz = Lat<Q>::D == 3 ? double(u[2 * a.n + s]) : 0.0;
+    } else {
+      ux = a.u0[0];
+      uy = a.u0[1];
+      uz = a.u0[2];
+    }
+    if (Lat<Q>::D == 2) uz = 0.0;
+    const int slot = LAY == LAY_AB ? i : Lat<Q>::opp(i);
+    if constexpr (NS) {
+      const double rho = a.rho ? a.rho[s] : 1.0;
+      stp<Q, ST>(a.fdst, slot, a.n, m, R(geq_dir<Q, double>(i, rho, ux, uy, uz)), R(a.fref));
+    }
+    stp<Q, ST>(a.hdst, slot, a.n, m, R(geq_dir<Q, double>(i, a.H[s], ux, uy, uz)), R(a.href));
+  }
+}
+
+// Stored post-collision state <-> FP64 [Q][n] (direction order).  Reading
+// out, solid nodes (cls) report zeros; writing in fills the layout's
+// post-collision addresses.
+template <int Q, int ST, int LAY, bool TO_STORAGE>
+__global__ void __launch_bounds__(256) k_convert(const KArgs a, const void *from, void *to, double ref) {
+  using R = typename StT<ST>::R;
+  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (m >= a.n) return;
+  const Node c = coords(a, m);
+  const bool solid = a.cls && a.cls[m] == CLS_SOLID;
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    int sl;
+    int64_t nd;
+    post_addr<Q, LAY>(a, c, m, i, sl, nd);
+    if constexpr (TO_STORAGE)
+      stp<Q, ST>(to, sl, a.n, nd, R(static_cast<const double *>(from)[i * a.n + m]), R(ref));
+    else
+      static_cast<double *>(to)[i * a.n + m] = solid ? 0.0 : double(ldp<Q, ST>(from, sl, a.n, nd, R(ref)));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Discrete adjoint of the advection-diffusion step (no geometry): node y
+// gathers lam_next_i(y + e_i) (transpose of the pull), applies the transposed
+// collision of node y and writes lam_prev(y); dJdQ(y) += b^T lam.
+// ---------------------------------------------------------------------------
+template <int Q, class R>
+__global__ void __launch_bounds__(256) k_adjoint(const KArgs a, const R *lam_next, R *lam_prev, double *dJdQ) {
+  constexpr int D = Lat<Q>::D;
+  const int64_t m = tile_of(a, blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (m >= a.n) return;
+  const Node c = coords(a, m);
+  R g[Q];
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    const int64_t d = shifted<Q>(a, c, i, +1);
+    g[Lat<Q>::slot(i)] = __builtin_nontemporal_load(lam_next + (int64_t)i * a.n + d);
+  }
+  R ux, uy, uz;
+  prescribed_u<Q, R>(a, m, ux, uy, uz);
+  const R dq = collide_adjoint<D, R>(g, rates<R>(a, false), ux, uy, uz);
+#pragma unroll
+  for (int i = 0; i < Q; i++) __builtin_nontemporal_store(g[Lat<Q>::slot(i)], lam_prev + (int64_t)i * a.n + m);
+  if (dJdQ) dJdQ[m] += double(dq);
+}
+
+// Objective J = 1/2 sum (H - H*)^2: seeds lam = dJ/dpre (every direction
+// H - H*), sets dJdQ = (H - H*)/2 (Q enters H as Q/2), leaves (H - H*)^2 in sq.
+template <int Q, class R>
+__global__ void __launch_bounds__(256) k_seed(const double *H, const double *Ht, int64_t n, R *lam, double *dJdQ,
+                                              double *sq) {
+  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (m >= n) return;
+  const double d = H[m] - Ht[m];
+#pragma unroll
+  for (int i = 0; i < Q; i++) lam[(int64_t)i * n + m] = R(d);
+  dJdQ[m] = 0.5 * d;
+  sq[m] = d * d;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers for one lattice
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+#define LBM_DISPATCH_LAY(LAY_VAL, CALL) \
+  switch (LAY_VAL) {                    \
+    case LAY_AB: {                      \
+      constexpr int LAY = LAY_AB;       \
+      return CALL;                      \
+    }                                   \
+    case LAY_AA_S: {                    \
+      constexpr int LAY = LAY_AA_S;     \
+      return CALL;                      \
+    }                                   \
+    case LAY_AA_N: {                    \
+      constexpr int LAY = LAY_AA_N;     \
+      return CALL;                      \
+    }                                   \
+    default:                            \
+      return hipErrorInvalidValue;      \
+  }
+
+template <int Q, int ST, bool NS, bool GEOM, int LAY>
+static hipError_t pass_t(int mode, const KArgs &a, hipStream_t s) {
+  const unsigned g = blocks_for(a.n, 256);
+  if (mode == MODE_STEP)
+    k_bulk<Q, ST, NS, GEOM, MODE_STEP, LAY><<<g, 256, 0, s>>>(a);
+  else if (mode == MODE_PRE)
+    k_bulk<Q, ST, NS, GEOM, MODE_PRE, LAY><<<g, 256, 0, s>>>(a);
+  else
+    k_bulk<Q, ST, NS, GEOM, MODE_MACRO, LAY><<<g, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int Q, int ST, bool NS, int LAY>
+static hipError_t special_t(int mode, const KArgs &a, hipStream_t s) {
+  if (a.nspecial == 0) return hipSuccess;
+  const unsigned g = blocks_for(a.nspecial, 64);
+  if (mode == MODE_STEP)
+    k_special<Q, ST, NS, MODE_STEP, LAY><<<g, 64, 0, s>>>(a);
+  else if (mode == MODE_PRE)
+    k_special<Q, ST, NS, MODE_PRE, LAY><<<g, 64, 0, s>>>(a);
+  else
+    k_special<Q, ST, NS, MODE_MACRO, LAY><<<g, 64, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int Q, int ST, bool NS, int LAY>
+static hipError_t fused_t(const KArgs &a, hipStream_t s) {
+  const int sblocks = (int)((blocks_for(a.nspecial, 256) + 7) / 8 * 8);
+  k_fused<Q, ST, NS, LAY><<<blocks_for(a.n, 256) + sblocks, 256, 0, s>>>(a, sblocks);
+  return hipGetLastError();
+}
+
+template <int Q, int ST, bool NS, int LAY>
+static hipError_t side_t(const KArgs &a, hipStream_t s) {
+  if (a.nspecial == 0) return hipSuccess;
+  k_side<Q, ST, NS, LAY><<<blocks_for(a.nspecial, 64), 64, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int Q, int ST, bool NS, int LAY>
+static hipError_t init_t(const InitArgs &a, hipStream_t s) {
+  k_init<Q, ST, NS, LAY><<<blocks_for(a.n, 256), 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int Q, int ST, int LAY>
+static hipError_t convert_t(bool to_storage, const KArgs &a, const void *from, void *to, double ref, hipStream_t s) {
+  if (to_storage)
+    k_convert<Q, ST, LAY, true><<<blocks_for(a.n, 256), 256, 0, s>>>(a, from, to, ref);
+  else
+    k_convert<Q, ST, LAY, false><<<blocks_for(a.n, 256), 256, 0, s>>>(a, from, to, ref);
+  return hipGetLastError();
+}
+
+template <int Q, class R>
+static hipError_t adjoint_t(const KArgs &a, const void *ln, void *lp, void *dq, hipStream_t s) {
+  k_adjoint<Q, R><<<blocks_for(a.n, 256), 256, 0, s>>>(a, static_cast<const R *>(ln), static_cast<R *>(lp),
+                                                         static_cast<double *>(dq));
+  return hipGetLastError();
+}
+
+// Launchers of one (lattice, storage) pair; LBM_INSTANTIATE below gives them
+// plain names in one translation unit per pair (compiled in parallel).
+template <int Q, int ST>
+struct Launch {
+  static hipError_t pass(bool ns, bool geom, int lay, int mode, const KArgs &a, hipStream_t s) {
+    if (ns) {
+      if (geom) return pass_lay<true, true>(lay, mode, a, s);
+      return pass_lay<true, false>(lay, mode, a, s);
+    }
+    if (geom) return pass_lay<false, true>(lay, mode, a, s);
+    return pass_lay<false, false>(lay, mode, a, s);
+  }
+  template <bool NS, bool GEOM>
+  static hipError_t pass_lay(int lay, int mode, const KArgs &a, hipStream_t s) {
+    LBM_DISPATCH_LAY(lay, (pass_t<Q, ST, NS, GEOM, LAY>(mode, a, s)))
+  }
+  static hipError_t special(bool ns, int lay, int mode, const KArgs &a, hipStream_t s) {
+    return ns ? special_lay<true>(lay, mode, a, s) : special_lay<false>(lay, mode, a, s);
+  }
+  template <bool NS>
+  static hipError_t special_lay(int lay, int mode, const KArgs &a, hipStream_t s) {
+    LBM_DISPATCH_LAY(lay, (special_t<Q, ST, NS, LAY>(mode, a, s)))
+  }
+  static hipError_t fused(bool ns, int lay, const KArgs &a, hipStream_t s) {
+    return ns ? fused_lay<true>(lay, a, s) : fused_lay<false>(lay, a, s);
+  }
+  template <bool NS>
+  static hipError_t fused_lay(int lay, const KArgs &a, hipStream_t s) {
+    LBM_DISPATCH_LAY(lay, (fused_t<Q, ST, NS, LAY>(a, s)))
+  }
+  static hipError_t side(bool ns, int lay, const KArgs &a, hipStream_t s) {
+    return ns ? side_lay<true>(lay, a, s) : side_lay<false>(lay, a, s);
+  }
+  template <bool NS>
+  static hipError_t side_lay(int lay, const KArgs &a, hipStream_t s) {
+    LBM_DISPATCH_LAY(lay, (side_t<Q, ST, NS, LAY>(a, s)))
+  }
+  static hipError_t init(bool ns, int lay, const InitArgs &a, hipStream_t s) {
+    if (lay == LAY_AB) return ns ? init_t<Q, ST, true, LAY_AB>(a, s) : init_t<Q, ST, false, LAY_AB>(a, s);
+    return ns ? init_t<Q, ST, true, LAY_AA_S>(a, s) : init_t<Q, ST, false, LAY_AA_S>(a, s);
+  }
+  static hipError_t convert(int lay, bool to_storage, const KArgs &a, const void *from, void *to, double ref,
+                            hipStream_t s) {
+    LBM_DISPATCH_LAY(lay, (convert_t<Q, ST, LAY>(to_storage, a, from, to, ref, s)))
+  }
+  // adjoint and seed depend on the arithmetic type only
+  static hipError_t adjoint(const KArgs &a, const void *ln, void *lp, void *dq, hipStream_t s) {
+    return adjoint_t<Q, typename StT<ST>::R>(a, ln, lp, dq, s);
+  }
+  static hipError_t seed(const double *H, const double *Ht, int64_t n, void *lam, void *dq, double *sq,
+                         hipStream_t s) {
+    using R = typename StT<ST>::R;
+    k_seed<Q, R><<<blocks_for(n, 256), 256, 0, s>>>(H, Ht, n, static_cast<R *>(lam), static_cast<double *>(dq), sq);
+    return hipGetLastError();
+  }
+};
+
+#define LBM_INSTANTIATE(Q, ST, NAME)                                                                          \
+  hipError_t NAME##_pass(bool ns, bool geom, int lay, int mode, const KArgs &a, hipStream_t s) {              \
+    return Launch<Q, ST>::pass(ns, geom, lay, mode, a, s);                                                    \
+  }                                                                                                           \
+  hipError_t NAME##_special(bool ns, int lay, int mode, const KArgs &a, hipStream_t s) {                      \
+    return Launch<Q, ST>::special(ns, lay, mode, a, s);                                                       \
+  }                                                                                                           \
+  hipError_t NAME##_fused(bool ns, int lay, const KArgs &a, hipStream_t s) {                                  \
+    return Launch<Q, ST>::fused(ns, lay, a, s);                                                               \
+  }                                                                                                           \
+  hipError_t NAME##_side(bool ns, int lay, const KArgs &a, hipStream_t s) {                                   \
+    return Launch<Q, ST>::side(ns, lay, a, s);                                                                \
+  }                                                                                                           \
+  hipError_t NAME##_init(bool ns, int lay, const InitArgs &a, hipStream_t s) {                                \
+    return Launch<Q, ST>::init(ns, lay, a, s);                                                                \
+  }                                                                                                           \
+  hipError_t NAME##_convert(int lay, bool to_storage, const KArgs &a, const void *from, void *to, double ref,  \
+                            hipStream_t s) {                                                                  \
+    return Launch<Q, ST>::convert(lay, to_storage, a, from, to, ref, s);                                      \
+  }                                                                                                           \
+  hipError_t NAME##_adjoint(const KArgs &a, const void *ln, void *lp, void *dq, hipStream_t s) {              \
+    return Launch<Q, ST>::adjoint(a, ln, lp, dq, s);                                                          \
+  }                                                                                                           \
+  hipError_t NAME##_seed(const double *H, const double *Ht, int64_t n, void *lam, void *dq, double *sq,       \
+                         hipStream_t s) {                                                                     \
+    return Launch<Q, ST>::seed(H, Ht, n, lam, dq, sq, s);                                                     \
+  }
+
+}  // namespace lbm

@@ -43,6 +43,10 @@ struct DevGroup {
 enum : int { NODE_FLUID = 0, NODE_SOLID = 1, NODE_EQ = 2, NODE_OUTLET = 3 };
 enum : uint8_t { CLS_BULK = 0, CLS_SOLID = 1, CLS_SPECIAL = 2 };
 
+// Streaming layouts (see lbm_impl.hpp): two arrays, or one array in the
+// swapped (S) or streamed (N) AA layout.
+enum : int { LAY_AB = 0, LAY_AA_S = 1, LAY_AA_N = 2 };
+
 // What a pass over the lattice produces.
 enum : int {
   MODE_STEP = 0,  // collide and store the post-collision state (next buffer)
@@ -66,6 +70,8 @@ struct KArgs {
   int64_t n;
   int32_t nx, ny, nz;
   int32_t with_uvel;       // advection velocity from the field (else u0)
+  int32_t tilemap;         // block -> tile order: 0 one slab per XCD, 1 rows per XCD
+  int32_t row_blocks;      // blocks per x-row (tilemap 1)
   double sf[27];           // rates of f, chimera order
   double sh[27];           // rates of h, chimera order
   float sf32[27];          // the same rates rounded for FP32 arithmetic
@@ -74,6 +80,10 @@ struct KArgs {
   double fref, href;       // deviation references (0 unless *_DEV storage)
   double *out0, *out1, *out2, *out3;  // MODE_PRE / MODE_MACRO outputs
   double *link_flux;       // MODE_MACRO: per-link injected energy
+  void *side_f;            // AA: g*_opp(i)(x_b) of f per link (arithmetic type)
+  void *side_h;            // AA: the same for h
+  void *side_u;            // AA: velocity at t-1 per boundary node, 2 entries
+                           //     per boundary-node record (node, upstream node)
 };
 
 struct InitArgs {
@@ -92,15 +102,17 @@ struct InitArgs {
 // storage codes (lbm_storage)
 enum : int { ST_FP64 = 0, ST_FP32 = 1, ST_FP32_DEV = 2, ST_FP16_DEV = 3 };
 
-// Launchers; return hipSuccess or the launch error.
-hipError_t launch_pass(int Q, int storage, bool ns, bool geom, int mode, const KArgs &a,
+// Launchers; return hipSuccess or the launch error.  lay: LAY_*.
+hipError_t launch_pass(int Q, int storage, bool ns, bool geom, int lay, int mode, const KArgs &a,
                        hipStream_t s);
-hipError_t launch_special(int Q, int storage, bool ns, int mode, const KArgs &a, hipStream_t s);
+hipError_t launch_special(int Q, int storage, bool ns, int lay, int mode, const KArgs &a, hipStream_t s);
 // D2Q9 step with geometry: boundary and bulk nodes in one launch.
-hipError_t launch_fused(int storage, bool ns, const KArgs &a, hipStream_t s);
-hipError_t launch_init(int Q, int storage, bool ns, const InitArgs &a, hipStream_t s);
-hipError_t launch_convert(int Q, int storage, bool to_storage, const void *from, void *to, int64_t n,
-                          double ref, const uint8_t *cls, hipStream_t s);
+hipError_t launch_fused(int Q, int storage, bool ns, int lay, const KArgs &a, hipStream_t s);
+// AA side buffers from the stored state.
+hipError_t launch_side(int Q, int storage, bool ns, int lay, const KArgs &a, hipStream_t s);
+hipError_t launch_init(int Q, int storage, bool ns, int lay, const InitArgs &a, hipStream_t s);
+hipError_t launch_convert(int Q, int storage, int lay, bool to_storage, const KArgs &a, const void *from, void *to,
+                          double ref, hipStream_t s);
 hipError_t launch_reduce(const double *rho, const double *H, const double *qx, int64_t n, int nx,
                          int ny, int nz, const int32_t *cols, int ncols, const double *link_flux,
                          const DevLink *links, int64_t nlinks, int group, double *partials,

@@ -205,7 +205,7 @@ class LBM:
     this object for its lifetime.
     """
 
-    def __init__(self, lattice=D2Q9, nx=64, ny=64, nz=1, *, device="cuda:0", stream=None, flags=None,
+    def __init__(self, lattice=D2Q9, nx=64, ny=64, nz=1, *, device="cuda:0", hip_stream=None, flags=None,
                  q=None, groups=(), **kw):
         import torch
 
@@ -224,7 +224,7 @@ class LBM:
         self.rdtype = torch.float64 if p.storage == FP64 else torch.float32
         nbytes = workspace_bytes(p)
         with torch.cuda.device(self.device):
-            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.stream = hip_stream if hip_stream is not None else torch.cuda.current_stream(self.device)
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             ctx = C.c_void_p()
             _check(_lib.lbm_create(C.byref(p), C.c_void_p(self.workspace.data_ptr()),

@@ -85,6 +85,45 @@ def circle_q(nx: int, ny: int, flags: np.ndarray, circles, Q: int = 9) -> np.nda
     return q
 
 
+def sphere_box(nx: int, ny: int, nz: int, center, r: float, inlet: bool = False):
+    """D3Q27 box, periodic, with a solid sphere (group 0, IBB/IABB, H = 2) and
+    optionally an EQ inlet plane x = 0 (group 1) and an outlet plane x = nx-1.
+    Returns (flags [n], q [27, n], groups); q is the smallest t in (0, 1] with
+    |x_b + t e_i - c| = r for links into the sphere (textbook quadratic, FP64)."""
+    n = nx * ny * nz
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx]
+    cx, cy, cz = center
+    flags = np.zeros((nz, ny, nx), np.uint16)
+    if inlet:
+        flags[:, :, 0] = flag(EQ, 1)
+        flags[:, :, nx - 1] = flag(OUTLET, 0)
+    ball = (x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2 <= r * r
+    flags[ball] = flag(SOLID, 0)
+    flags = flags.reshape(-1)
+    q = np.full((27, n), 0.5)
+    solid = (flags & 15) == SOLID
+    X, Y, Z = x.reshape(-1), y.reshape(-1), z.reshape(-1)
+    for a in range(1, 27):
+        ex, ey, ez = (int(v) for v in D3Q27_E[a])
+        tgt = ((X + ex) % nx) + nx * (((Y + ey) % ny) + ny * ((Z + ez) % nz))
+        cut = (~solid) & solid[tgt]
+        for m in np.nonzero(cut)[0]:
+            dx, dy, dz = X[m] - cx, Y[m] - cy, Z[m] - cz
+            A = ex * ex + ey * ey + ez * ez
+            B = 2.0 * (dx * ex + dy * ey + dz * ez)
+            Cc = dx * dx + dy * dy + dz * dz - r * r
+            disc = B * B - 4.0 * A * Cc
+            if disc < 0:
+                continue
+            sq = math.sqrt(disc)
+            ts = [t for t in ((-B - sq) / (2 * A), (-B + sq) / (2 * A)) if 0.0 < t <= 1.0]
+            if ts:
+                q[a, m] = min(ts)
+    groups = [dict(f_scheme=1, h_scheme=1, H_w=2.0), dict(f_scheme=0, h_scheme=0, rho_w=1.0,
+                                                           u_w=(0.02, 0.0, 0.0), H_w=1.0)]
+    return flags, q, groups
+
+
 # ---------------------------------------------------------------------------
 # Workloads
 # ---------------------------------------------------------------------------

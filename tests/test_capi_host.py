@@ -48,7 +48,7 @@ def test_version_and_workspace(L):
     (dict(with_ns=True, nu=0.0), "viscosity"),
     (dict(storage=7), "storage"),
     (dict(lattice=15), "lattice"),
-    (dict(stream=1), "stream mode"),
+    (dict(stream=7), "stream mode"),
     (dict(with_source=True, with_ns=True, nu=0.1), "source"),
 ])
 def test_param_validation(L, kw, msg):
@@ -102,6 +102,24 @@ def test_link_table_bit_exact_vs_oracle(L, oracle, Q, dims):
     has_link = np.zeros(len(flags), bool)
     has_link[ref["node"]] = True
     assert ns == int(np.count_nonzero((t != 1) & ((t == 2) | (t == 3) | has_link)))
+
+
+def test_aa_layout_geometry(L, oracle):
+    """In the in-place (AA) layout an outlet's thread also updates its upstream
+    node, which must then be a plain fluid node; the cut links are unchanged."""
+    flags, q, groups, u = __import__("paper_2203_01316_amd.workloads", fromlist=["x"]).channel(64, 24, 20, 12, 4.0)
+    pab = L.make_params(L.D2Q9, 64, 24, k=0.01)
+    paa = L.make_params(L.D2Q9, 64, 24, k=0.01, stream=L.STREAM_AA)
+    assert L.build_links(paa, flags, q, 3).tobytes() == L.build_links(pab, flags, q, 3).tobytes()
+    nl_ab, ns_ab = L.count_geometry(pab, flags)
+    nl_aa, ns_aa = L.count_geometry(paa, flags)
+    assert nl_aa == nl_ab and ns_aa <= ns_ab
+    bad = flags.copy().reshape(24, 64)
+    bad[5, 62] = L.EQ  # upstream of the outlet node (63, 5)
+    with pytest.raises(L.LBMError) as e:
+        L.build_links(paa, bad.reshape(-1), q, 3)
+    assert "AA layout" in str(e.value) and "outlet node" in str(e.value)
+    L.build_links(pab, bad.reshape(-1), q, 3)  # fine for two arrays
 
 
 def test_geometry_errors_name_the_index(L):

@@ -1,0 +1,174 @@
+"""In-place (AA) streaming against two-array (AB) streaming: the same
+arithmetic on every node, so the canonical states, the stored post-collision
+states, the macroscopic fields and the reductions agree bit for bit after odd
+and even step counts, with walls, interpolated walls, EQ nodes and outlets."""
+import numpy as np
+import pytest
+
+from paper_2203_01316_amd import workloads as W
+
+from gpu_common import f32, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2203_01316_amd import lbm
+    return lbm
+
+
+def _both(L, make):
+    return make(L.STREAM_AB), make(L.STREAM_AA)
+
+
+def _same(L, ab, aa, lattices, exact=True, cols=(), group=0):
+    for lat in lattices:
+        for which in ("pre", "post"):
+            x = ab.populations(lat, which).cpu().numpy()
+            y = aa.populations(lat, which).cpu().numpy()
+            if exact:
+                assert np.array_equal(x, y), (lat, which, np.abs(x - y).max())
+            else:
+                assert rel_l2(y, x) < 1e-6, (lat, which, rel_l2(y, x))
+    ra = ab.reduce(group=group, columns=cols)
+    rb = aa.reduce(group=group, columns=cols)
+    if exact:
+        assert np.array_equal(ra, rb), (ra, rb)
+    _, ua, Ha = ab.macroscopic()
+    _, ub, Hb = aa.macroscopic()
+    if exact:
+        assert np.array_equal(Ha.cpu().numpy(), Hb.cpu().numpy())
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_aa_periodic_hill(L, storage):
+    H0 = W.gaussian_hill(64, 8.0, 0.5, None, (0.05, 0.02), 0.01, 0.0)
+
+    def make(stream):
+        g = L.LBM(9, 64, 64, storage=storage, k=0.01, u0=(0.05, 0.02, 0), stream=stream)
+        g.init(H0)
+        return g
+
+    ab, aa = _both(L, make)
+    for k in (1, 6, 13):
+        ab.step(k)
+        aa.step(k)
+        _same(L, ab, aa, ("h",))
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_aa_channel(L, storage):
+    flags, q, groups, u = W.channel(160, 48, 40, 24, 7.5, 0.05)
+    uu = f32(u) if storage == "fp32" else u
+
+    def make(stream):
+        g = L.LBM(9, 160, 48, storage=storage, k=0.005, u_mode=1, flags=flags, q=q, groups=groups, stream=stream)
+        g.set_velocity(uu)
+        g.init(np.zeros(160 * 48))
+        return g
+
+    ab, aa = _both(L, make)
+    for k in (1, 2, 37):
+        ab.step(k)
+        aa.step(k)
+        _same(L, ab, aa, ("h",), cols=(10, 80, 159), group=2)
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_aa_coupled_cylinder(L, storage):
+    flags, q, groups, u, rho0, H0 = W.heated_cylinder(192, 96, 9.5, u_in=0.04, amp=1e-3, seed=0)
+    uu = f32(u) if storage == "fp32" else u
+
+    def make(stream):
+        g = L.LBM(9, 192, 96, storage=storage, with_ns=True, nu=0.04, k=0.06, flags=flags, q=q, groups=groups,
+                  stream=stream)
+        g.set_velocity(uu)
+        g.init(H0, u=uu, rho=rho0)
+        return g
+
+    ab, aa = _both(L, make)
+    for k in (1, 4, 51):
+        ab.step(k)
+        aa.step(k)
+        _same(L, ab, aa, ("f", "h"), cols=(5, 150), group=1)
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_aa_d3q27_sphere(L, storage):
+    nx, ny, nz = 20, 14, 12
+    flags, q, groups = W.sphere_box(nx, ny, nz, (9.3, 6.6, 5.8), 3.4, inlet=True)
+    n = nx * ny * nz
+    rng = np.random.default_rng(60)
+    u = np.zeros((3, n))
+    u[0] = 0.02
+    u = f32(u) if storage == "fp32" else u
+    H0 = 1 + 0.1 * rng.uniform(size=n)
+
+    def make(stream):
+        g = L.LBM(27, nx, ny, nz, storage=storage, with_ns=True, nu=0.03, k=0.02, flags=flags, q=q, groups=groups,
+                  stream=stream)
+        g.init(H0, u=u, rho=np.ones(n))
+        return g
+
+    ab, aa = _both(L, make)
+    for k in (1, 2, 9):
+        ab.step(k)
+        aa.step(k)
+        _same(L, ab, aa, ("f", "h"), cols=(3, 15), group=0)
+
+
+def test_aa_restart_and_set_at_odd_phase(L):
+    flags, q, groups, u, rho0, H0 = W.heated_cylinder(96, 48, 6.5, cx=24, cy=24, u_in=0.04, amp=1e-3, seed=0)
+    uu = f32(u)
+
+    def make(stream):
+        g = L.LBM(9, 96, 48, storage="fp32", with_ns=True, nu=0.04, k=0.05, flags=flags, q=q, groups=groups,
+                  stream=stream)
+        g.set_velocity(uu)
+        g.init(H0, u=uu, rho=rho0)
+        return g
+
+    ab, aa = _both(L, make)
+    ab.step(7)
+    aa.step(7)
+    snap = aa.save_state()
+    aa.step(10)
+    ref = aa.populations("h", "post").cpu().numpy()
+    aa.load_state(snap)
+    assert aa.t == 7
+    aa.step(10)
+    assert np.array_equal(aa.populations("h", "post").cpu().numpy(), ref)
+    # replace the state of both contexts at odd AA phase, then continue
+    fpost = ab.populations("f", "post")
+    hpost = ab.populations("h", "post")
+    ab.step(3)
+    aa2 = make(L.STREAM_AA)
+    aa2.step(1)
+    aa2.set_populations("f", fpost, t=17)
+    aa2.set_populations("h", hpost, t=17)
+    ab2 = make(L.STREAM_AB)
+    ab2.set_populations("f", fpost, t=17)
+    ab2.set_populations("h", hpost, t=17)
+    ab2.step(3)
+    aa2.step(3)
+    _same(L, ab2, aa2, ("f", "h"))
+
+
+def test_aa_fp16_dev_close_to_ab(L):
+    flags, q, groups, u, rho0, H0 = W.heated_cylinder(192, 96, 9.5, u_in=0.04, amp=1e-3, seed=0)
+    uu = f32(u)
+
+    def make(stream):
+        g = L.LBM(9, 192, 96, storage="fp16_dev", with_ns=True, nu=0.04, k=0.06, flags=flags, q=q, groups=groups,
+                  stream=stream, rho_ref=1.0, H_ref=10.0)
+        g.set_velocity(uu)
+        g.init(H0, u=uu, rho=rho0)
+        return g
+
+    ab, aa = _both(L, make)
+    ab.step(41)
+    aa.step(41)
+    _same(L, ab, aa, ("f", "h"), exact=False)

@@ -266,3 +266,27 @@ def test_divergence_is_reported(L):
     with pytest.raises(L.LBMError) as e:
         g.reduce()
     assert e.value.status == L.EDIVERGED
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_d3q27_sphere_inlet_outlet(L, oracle, storage, tol):
+    """D3Q27 coupled lattices with an interpolated sphere (IBB/IABB), an EQ inlet
+    plane and an outlet plane (the separate boundary-node kernel of D3Q27)."""
+    nx, ny, nz = 20, 14, 12
+    flags, q, groups = W.sphere_box(nx, ny, nz, (9.3, 6.6, 5.8), 3.4, inlet=True)
+    n = nx * ny * nz
+    u = np.zeros((3, n))
+    u[0] = 0.02
+    H0 = 1 + 0.1 * np.random.default_rng(61).uniform(size=n)
+    g, o = pair(L, oracle, Q=27, dims=(nx, ny, nz), storage=storage, with_ns=True, nu=0.03, k=0.02, flags=flags,
+                q=q, groups=groups, H0=H0, u_init=u, rho0=np.ones(n))
+    g.step(25)
+    o.step(25)
+    fo, ho = o.pre()
+    assert rel_l2(gpu_pre(g, "f"), fluid_only(fo, o.flags)) < tol
+    assert rel_l2(gpu_pre(g, "h"), fluid_only(ho, o.flags)) < tol
+    red = g.reduce(group=0, columns=[3, 15])
+    _, ho2, flux = o.pre(with_flux=True)
+    lk = o.links()
+    assert red[2] == pytest.approx(flux[lk["group"] == 0].sum(), rel=max(tol, 1e-10) * 10)
+    assert red[3] == pytest.approx(o.section_flux(3, ho2), rel=max(tol, 1e-10) * 10)
