@@ -32,7 +32,7 @@ def source_digest() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2203_01316_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
+        if name.endswith((".hip", ".hpp")) or name == "build.py":
             with open(os.path.join(csrc, name), "rb") as fh:
                 h.update(fh.read())
     return h.hexdigest()[:16]
@@ -203,6 +203,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP16, D3Q27 and adjoint legs")
+    ap.add_argument("--extra-scale", type=float, default=1.0, help="scale the step counts of those legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: only one GPU is supported in this build (got --gpus {args.gpus}); the kernel "
@@ -287,9 +288,11 @@ def main():
     if not args.no_extra:
         del g
         torch.cuda.empty_cache()
-        out["also"] = [leg_cylinder(torch, L, W, np, "fp16_dev", nx, ny, 1000),
-                       leg_tgv(torch, L, W, "fp32", 256, 100), leg_tgv(torch, L, W, "fp16_dev", 256, 100)]
-        out["adjoint"] = leg_adjoint(torch, L, np)
+        sc = args.extra_scale
+        out["also"] = [leg_cylinder(torch, L, W, np, "fp16_dev", nx, ny, max(10, int(1000 * sc))),
+                       leg_tgv(torch, L, W, "fp32", 256, max(5, int(100 * sc))),
+                       leg_tgv(torch, L, W, "fp16_dev", 256, max(5, int(100 * sc)))]
+        out["adjoint"] = leg_adjoint(torch, L, np, steps=max(90, int(2000 * sc)))
         out["adjoint_forward_ratio"] = out["adjoint"]["no_replay"]["ratio"]
     if not args.no_cpu:
         inputs = (flags, q, groups, uf.astype(np.float64), rho0, H0, nx, ny, nu, k)

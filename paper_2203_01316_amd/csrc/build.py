@@ -13,6 +13,9 @@ SOURCES = [f"lbm_q{q}_{st}.hip" for q in (9, 27) for st in ("fp64", "fp32", "fp3
     "lbm_kernels.hip", "lbm_host.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+         # multiply-adds fuse within one source expression only, so a node's
+         # arithmetic does not depend on the kernel it is inlined into
+         "-ffp-contract=on",
          # packed FP32 instructions stay disabled in all device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", HERE]

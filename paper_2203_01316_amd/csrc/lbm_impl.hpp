@@ -349,10 +349,7 @@ template <int Q, int ST, bool NS, bool GEOM, int MODE, int LAY, bool BITS = fals
 __device__ __forceinline__ void bulk_node(const KArgs &a, int64_t m) {
   using R = typename StT<ST>::R;
   if (m >= a.n) return;
-  if constexpr (BITS) {
-    // step kernel: solid and boundary nodes are skipped (1 bit per node)
-    if ((a.skip[m >> 5] >> (m & 31)) & 1u) return;
-  } else if constexpr (GEOM) {
+  if constexpr (GEOM && !BITS) {
     const uint8_t c = a.cls[m];
     if (c == CLS_SPECIAL) return;
     if (c == CLS_SOLID) {
@@ -360,6 +357,11 @@ __device__ __forceinline__ void bulk_node(const KArgs &a, int64_t m) {
       return;
     }
   }
+  // step kernel with geometry: solid and boundary nodes are skipped (1 bit
+  // per node); the mask word is loaded alongside the populations so its
+  // latency overlaps theirs (the pull of a skipped node is in bounds, unused)
+  uint32_t skipword = 0;
+  if constexpr (BITS) skipword = a.skip[m >> 5];
   const Node c = coords(a, m);
   R f[Q], h[Q];
 #pragma unroll
@@ -370,6 +372,8 @@ __device__ __forceinline__ void bulk_node(const KArgs &a, int64_t m) {
     if constexpr (NS) f[i] = ldp<Q, ST>(a.fsrc, sl, a.n, nd, R(a.fref));
     h[i] = ldp<Q, ST>(a.hsrc, sl, a.n, nd, R(a.href));
   }
+  if constexpr (BITS)
+    if ((skipword >> (m & 31)) & 1u) return;
   finish_node<Q, ST, NS, MODE, LAY>(a, c, m, f, h);
 }
 
@@ -546,13 +550,20 @@ __global__ void __launch_bounds__(64) k_special(const KArgs a) {
 // nodes, whose long chains of dependent loads then overlap the bulk stream
 // instead of running after it.
 template <int Q, int ST, bool NS, int LAY>
-__global__ void __launch_bounds__(256) k_fused(const KArgs a, int sblocks) {
+__device__ __forceinline__ void fused_body(const KArgs &a, int sblocks) {
   if ((int)blockIdx.x < sblocks) {
     special_node<Q, ST, NS, MODE_STEP, LAY>(a, (int64_t)blockIdx.x * 256 + threadIdx.x);
     return;
   }
   const int64_t tile = tile_of(a, blockIdx.x - sblocks, gridDim.x - sblocks);
   bulk_node<Q, ST, NS, true, MODE_STEP, LAY, true>(a, tile * 256 + threadIdx.x);
+}
+
+// (The scalar state of the boundary path limits this launch to 7 waves per
+// SIMD where the bulk kernel runs 8; forcing 8 measured slower on MI355X.)
+template <int Q, int ST, bool NS, int LAY>
+__global__ void __launch_bounds__(256) k_fused(const KArgs a, int sblocks) {
+  fused_body<Q, ST, NS, LAY>(a, sblocks);
 }
 
 // AA side buffers from the stored state (after init, set or load).
