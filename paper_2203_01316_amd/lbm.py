@@ -198,6 +198,16 @@ def _groups_struct(groups):
     return arr
 
 
+def nusselt(q_surface: float, q_in: float, q_out: float, k: float, T_wall: float, T_in: float) -> float:
+    """Nusselt number of a heated cylinder from the FP64 reductions of
+    lbm_reduce (Sec. 4.4): Nu = varsigma D / k with varsigma = qdot / (pi D
+    (T_wall - T_in)), so Nu = qdot / (pi k (T_wall - T_in)); qdot is the mean
+    of the heater flux and the net section flux q_in - q_out."""
+    import math
+    qdot = 0.5 * (q_surface + (q_in - q_out))
+    return qdot / (math.pi * k * (T_wall - T_in))
+
+
 class LBM:
     """One context of liblbm.so on one device and stream.
 
