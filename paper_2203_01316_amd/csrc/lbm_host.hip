@@ -52,7 +52,7 @@ int chimera_index(int Q, const int m[3]) { return Q == 27 ? m[0] * 9 + m[1] * 3 
 struct Layout {
   size_t pop_bytes;  // one copy of one lattice
   size_t off_pop[2][2];
-  size_t off_cls, off_skip, off_links, off_special, off_groups, off_rho, off_H, off_qx, off_flux, off_part,
+  size_t off_cls, off_links, off_walls, off_special, off_groups, off_rho, off_H, off_qx, off_flux, off_part,
       off_res, off_cols, off_side_f, off_side_h, off_side_u;
   size_t total;
 };
@@ -148,10 +148,11 @@ Layout layout(const lbm_params *p) {
     }
   L.off_cls = off;
   off += align_up((size_t)n);
-  L.off_skip = off;
-  off += align_up(sizeof(uint32_t) * (size_t)((n + 31) / 32));
   L.off_links = off;
   off += align_up(sizeof(DevLink) * (size_t)p->max_links);
+  L.off_walls = off;
+  off += align_up((p->storage == LBM_FP64 ? sizeof(DevWall<double>) : sizeof(DevWall<float>)) *
+                  (size_t)p->max_links);
   L.off_special = off;
   off += align_up(sizeof(DevSpecial) * (size_t)p->max_special);
   L.off_groups = off;
@@ -188,7 +189,6 @@ struct Geometry {
   std::vector<DevLink> links;
   std::vector<DevSpecial> special;
   std::vector<uint8_t> cls;
-  std::vector<uint32_t> skip;  // 1 bit per node: not a bulk node
   bool any = false;
 };
 
@@ -241,6 +241,27 @@ bool build_geometry_q(const lbm_params *p, const uint16_t *flags, const double *
     }
     return true;
   };
+  // upstream node of an outlet (x - 1, periodic in x)
+  auto upstream = [&](int64_t n) -> int64_t { return n % p->nx == 0 ? n + p->nx - 1 : n - 1; };
+  // An outlet node is handled by the bulk threads when neither it nor its
+  // upstream node has cut links, the upstream node is a plain fluid node, and
+  // both lie in one wavefront of 64 consecutive nodes (n % 64 != 0, x != 0):
+  // the outlet's lane then reads the upstream populations from the previous
+  // lane.  EQ nodes without cut links are handled there too.
+  auto bulk_outlet = [&](int64_t n, uint32_t mask, bool *ok) -> bool {
+    *ok = true;
+    if (mask || n % p->nx == 0 || n % 64 == 0) return false;
+    const int64_t up = n - 1;
+    if (ntype(flags, up) != LBM_NODE_FLUID) return false;
+    uint32_t umask;
+    if (!links_of(up, &umask, false)) {
+      *ok = false;
+      return false;
+    }
+    return umask == 0;
+  };
+  std::vector<char> listed_outlet;
+  if (aa && flags) listed_outlet.assign((size_t)N, 0);
   for (int64_t n = 0; flags && n < N; n++) {
     const int t = ntype(flags, n);
     if (t == LBM_NODE_SOLID) {
@@ -254,11 +275,21 @@ bool build_geometry_q(const lbm_params *p, const uint16_t *flags, const double *
     cl += __builtin_popcount(mask);
     if (t == LBM_NODE_EQ || t == LBM_NODE_OUTLET || mask) {
       G->any = true;
+      if (t == LBM_NODE_OUTLET && ntype(flags, upstream(n)) == LBM_NODE_SOLID)
+        return set_err(err, "outlet node %lld: upstream node %lld is solid", (long long)n, (long long)upstream(n));
+      if (t == LBM_NODE_EQ && mask == 0 && ngroup(flags, n) <= CLS_EQ_MAX_GROUP) {
+        if (want_links) G->cls[n] = (uint8_t)(CLS_EQ + ngroup(flags, n));
+        continue;
+      }
       if (t == LBM_NODE_OUTLET) {
-        const int64_t x = n % p->nx;
-        const int64_t up = x == 0 ? n + p->nx - 1 : n - 1;
-        if (ntype(flags, up) == LBM_NODE_SOLID)
-          return set_err(err, "outlet node %lld: upstream node %lld is solid", (long long)n, (long long)up);
+        bool ok;
+        const bool in_bulk = bulk_outlet(n, mask, &ok);
+        if (!ok) return false;
+        if (in_bulk) {
+          if (want_links) G->cls[n] = CLS_OUTLET;
+          continue;
+        }
+        if (aa) listed_outlet[n] = 1;
       }
       if (want_links) {
         DevSpecial s;
@@ -275,26 +306,31 @@ bool build_geometry_q(const lbm_params *p, const uint16_t *flags, const double *
     }
   }
   if (aa && flags) {
-    // AA: an outlet node's thread also updates its upstream node, which then
-    // needs no record of its own (see lbm_impl.hpp)
-    std::vector<char> absorbed(want_links ? (size_t)N : 0, 0);
+    // AA: the thread of a listed outlet node also updates its upstream node,
+    // which then needs no record of its own (see lbm_impl.hpp)
+    std::vector<char> absorbed((size_t)N, 0);
     for (int64_t n = 0; n < N; n++) {
       if (ntype(flags, n) != LBM_NODE_OUTLET) continue;
-      const int64_t x = n % p->nx;
-      const int64_t up = x == 0 ? n + p->nx - 1 : n - 1;
+      const int64_t up = upstream(n);
       if (ntype(flags, up) != LBM_NODE_FLUID)
         return set_err(err, "AA layout: outlet node %lld needs a FLUID upstream node (node %lld)", (long long)n,
                        (long long)up);
-      if (want_links) {
-        absorbed[up] = 1;
-        G->cls[up] = CLS_SPECIAL;
-      }
+      if (!listed_outlet[n]) continue;
+      absorbed[up] = 1;
+      if (want_links) G->cls[up] = CLS_SPECIAL;
+    }
+    // an absorbed node that had a record of its own (a fluid node with cut
+    // links) loses it
+    for (int64_t n = 0; n < N; n++) {
+      if (!absorbed[n]) continue;
+      uint32_t m;
+      if (!links_of(n, &m, false)) return false;
+      if (m) cs--;
     }
     if (want_links) {
       std::vector<DevSpecial> kept;
       for (const auto &sp : G->special)
         if (!absorbed[sp.node]) kept.push_back(sp);
-      cs = (int64_t)kept.size();
       G->special.swap(kept);
     }
   }
@@ -302,8 +338,7 @@ bool build_geometry_q(const lbm_params *p, const uint16_t *flags, const double *
     // upstream link ranges of outlet nodes (links are sorted by node)
     for (auto &s : G->special) {
       if (s.type != LBM_NODE_OUTLET) continue;
-      const int64_t x = s.node % p->nx;
-      const int64_t up = x == 0 ? s.node + p->nx - 1 : s.node - 1;
+      const int64_t up = upstream(s.node);
       size_t lo = 0, hi = G->links.size();
       while (lo < hi) {
         const size_t mid = (lo + hi) / 2;
@@ -318,6 +353,24 @@ bool build_geometry_q(const lbm_params *p, const uint16_t *flags, const double *
   if (nlinks) *nlinks = cl;
   if (nspecial) *nspecial = cs;
   return true;
+}
+
+// Per-link wall records in the arithmetic type R.  A link takes the plain
+// (anti-)bounce-back rule when its group asks for it, when x_f = x_b - e_i is
+// solid (one-node gap) or when q = 1/2, where both branches of the
+// interpolated rules reduce to it (Sec. 3).
+template <class R>
+void wall_records(const std::vector<DevLink> &links, const std::vector<DevGroup> &groups, std::vector<char> *out) {
+  out->assign(sizeof(DevWall<R>) * links.size(), 0);
+  DevWall<R> *w = reinterpret_cast<DevWall<R> *>(out->data());
+  for (size_t l = 0; l < links.size(); l++) {
+    const DevLink &k = links[l];
+    const DevGroup &g = groups[k.group];
+    const bool plain = k.xf_solid || k.q == 0.5;
+    w[l].q = R(k.q);
+    w[l].H_w = R(g.H_w);
+    w[l].interp = (g.f_scheme == LBM_WALL_IBB && !plain ? 1 : 0) | (g.h_scheme == LBM_WALL_IABB && !plain ? 2 : 0);
+  }
 }
 
 bool build_geometry(const lbm_params *p, const uint16_t *flags, const double *q, int n_groups,
@@ -400,11 +453,11 @@ static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   a.side_h = ctx->ws + ctx->L.off_side_h;
   a.side_u = ctx->ws + ctx->L.off_side_u;
   a.cls = ctx->geom ? reinterpret_cast<const uint8_t *>(ctx->ws + ctx->L.off_cls) : nullptr;
-  a.skip = ctx->geom ? reinterpret_cast<const uint32_t *>(ctx->ws + ctx->L.off_skip) : nullptr;
   a.uvel = ctx->uvel;
   a.with_uvel = ctx->uvel != nullptr;
   a.src = ctx->p.with_source ? ctx->src : nullptr;
   a.links = reinterpret_cast<const DevLink *>(ctx->ws + ctx->L.off_links);
+  a.walls = ctx->ws + ctx->L.off_walls;
   a.special = reinterpret_cast<const DevSpecial *>(ctx->ws + ctx->L.off_special);
   a.groups = reinterpret_cast<const DevGroup *>(ctx->ws + ctx->L.off_groups);
   a.nspecial = ctx->geom ? ctx->nspecial : 0;
@@ -596,6 +649,7 @@ lbm_status lbm_set_geometry(lbm_ctx *ctx, const uint16_t *flags, const double *q
     }
   }
   Geometry G;
+  std::vector<char> walls;
   int64_t nl = 0, ns = 0;
   if (!build_geometry(&ctx->p, flags, q, n_groups, true, &G, &nl, &ns, &ctx->err)) return LBM_EINVAL;
   if (nl > ctx->p.max_links || ns > ctx->p.max_special) {
@@ -610,16 +664,18 @@ lbm_status lbm_set_geometry(lbm_ctx *ctx, const uint16_t *flags, const double *q
   HIP_TRY(ctx, hipMemcpyAsync(ctx->ws + ctx->L.off_groups, dg.data(), sizeof(DevGroup) * dg.size(),
                               hipMemcpyHostToDevice, ctx->stream), "copy groups");
   if (G.any) {
-    G.skip.assign((size_t)((ctx->n + 31) / 32), 0u);
-    for (int64_t m = 0; m < ctx->n; m++)
-      if (G.cls[m] != CLS_BULK) G.skip[m >> 5] |= 1u << (m & 31);
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->ws + ctx->L.off_skip, G.skip.data(), sizeof(uint32_t) * G.skip.size(),
-                                hipMemcpyHostToDevice, ctx->stream), "copy skip mask");
     HIP_TRY(ctx, hipMemcpyAsync(ctx->ws + ctx->L.off_cls, G.cls.data(), G.cls.size(), hipMemcpyHostToDevice,
                                 ctx->stream), "copy node classes");
-    if (nl)
+    if (nl) {
       HIP_TRY(ctx, hipMemcpyAsync(ctx->ws + ctx->L.off_links, G.links.data(), sizeof(DevLink) * nl,
                                   hipMemcpyHostToDevice, ctx->stream), "copy links");
+      if (ctx->p.storage == LBM_FP64)
+        wall_records<double>(G.links, dg, &walls);
+      else
+        wall_records<float>(G.links, dg, &walls);
+      HIP_TRY(ctx, hipMemcpyAsync(ctx->ws + ctx->L.off_walls, walls.data(), walls.size(), hipMemcpyHostToDevice,
+                                  ctx->stream), "copy wall records");
+    }
     if (ns)
       HIP_TRY(ctx, hipMemcpyAsync(ctx->ws + ctx->L.off_special, G.special.data(), sizeof(DevSpecial) * ns,
                                   hipMemcpyHostToDevice, ctx->stream), "copy boundary nodes");

@@ -345,23 +345,42 @@ __device__ __forceinline__ int64_t tile_of(const KArgs &a, int64_t b, int64_t nb
 // ---------------------------------------------------------------------------
 // Bulk nodes
 // ---------------------------------------------------------------------------
-template <int Q, int ST, bool NS, bool GEOM, int MODE, int LAY, bool BITS = false>
+// Populations of an EQ node of group g after streaming (Sec. 3): the
+// equilibrium of the group's values, with the per-node velocity field when one
+// is set, else the group's velocity (with f) or the prescribed one.
+template <int Q, int ST, bool NS>
+__device__ __forceinline__ void eq_node(const KArgs &a, int64_t m, int g, typename StT<ST>::R *f,
+                                        typename StT<ST>::R *h) {
+  using R = typename StT<ST>::R;
+  const DevGroup &G = a.groups[g];
+  R ux, uy, uz;
+  if (NS && !a.with_uvel) {
+    ux = R(G.u_w[0]);
+    uy = R(G.u_w[1]);
+    uz = Lat<Q>::D == 3 ? R(G.u_w[2]) : R(0);
+  } else {
+    prescribed_u<Q, R>(a, m, ux, uy, uz);
+  }
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    if constexpr (NS) f[i] = geq_dir<Q, R>(i, R(G.rho_w), ux, uy, uz);
+    h[i] = geq_dir<Q, R>(i, R(G.H_w), ux, uy, uz);
+  }
+}
+
+// One node per thread, m = tile * 256 + threadIdx.x, so lane = m % 64.  With
+// geometry the class byte is loaded alongside the populations so that its
+// latency overlaps theirs (the pulls of a solid or listed node are in bounds
+// and unused).  Bulk-class EQ nodes take their equilibrium; a bulk-class
+// outlet node (zero gradient along x) takes the e_x < 0 populations of its
+// upstream node x - 1, which the previous lane of the same wavefront has just
+// pulled (that node has no cut links, so these are its final values).
+template <int Q, int ST, bool NS, bool GEOM, int MODE, int LAY>
 __device__ __forceinline__ void bulk_node(const KArgs &a, int64_t m) {
   using R = typename StT<ST>::R;
   if (m >= a.n) return;
-  if constexpr (GEOM && !BITS) {
-    const uint8_t c = a.cls[m];
-    if (c == CLS_SPECIAL) return;
-    if (c == CLS_SOLID) {
-      solid_node<Q, NS, MODE>(a, m);
-      return;
-    }
-  }
-  // step kernel with geometry: solid and boundary nodes are skipped (1 bit
-  // per node); the mask word is loaded alongside the populations so its
-  // latency overlaps theirs (the pull of a skipped node is in bounds, unused)
-  uint32_t skipword = 0;
-  if constexpr (BITS) skipword = a.skip[m >> 5];
+  uint8_t cl = CLS_BULK;
+  if constexpr (GEOM) cl = a.cls[m];
   const Node c = coords(a, m);
   R f[Q], h[Q];
 #pragma unroll
@@ -372,8 +391,26 @@ __device__ __forceinline__ void bulk_node(const KArgs &a, int64_t m) {
     if constexpr (NS) f[i] = ldp<Q, ST>(a.fsrc, sl, a.n, nd, R(a.fref));
     h[i] = ldp<Q, ST>(a.hsrc, sl, a.n, nd, R(a.href));
   }
-  if constexpr (BITS)
-    if ((skipword >> (m & 31)) & 1u) return;
+  if constexpr (GEOM) {
+    if (__ballot(cl == CLS_OUTLET)) {
+#pragma unroll
+      for (int i = 0; i < Q; i++) {
+        if (Lat<Q>::ex(i) >= 0) continue;
+        if constexpr (NS) {
+          const R fu = __shfl_up(f[i], 1);
+          if (cl == CLS_OUTLET) f[i] = fu;
+        }
+        const R hu = __shfl_up(h[i], 1);
+        if (cl == CLS_OUTLET) h[i] = hu;
+      }
+    }
+    if (cl == CLS_SOLID) {
+      solid_node<Q, NS, MODE>(a, m);
+      return;
+    }
+    if (cl == CLS_SPECIAL) return;
+    if (cl >= CLS_EQ) eq_node<Q, ST, NS>(a, m, cl - CLS_EQ, f, h);
+  }
   finish_node<Q, ST, NS, MODE, LAY>(a, c, m, f, h);
 }
 
@@ -390,10 +427,16 @@ __global__ void __launch_bounds__(256) k_bulk(const KArgs a) {
 // lb, one per set bit in increasing direction), direction order.  side_node
 // indexes the node's velocity entry of the AA side buffer.  flux (optional)
 // receives h_opp(x_b, t) - h*_i(x_b, t-1) per link.
+//
+// Every value read here depends only on (m, lb, mask), so all loads are issued
+// before the first use: while the bulk of the step saturates HBM a memory
+// round trip takes microseconds, and a chain of them per link (record, group,
+// then populations) would outlast the bulk nodes of the same launch.
 template <int Q, int ST, bool NS, int LAY>
 __device__ __forceinline__ void pull_links(const KArgs &a, int64_t m, int32_t lb, uint32_t mask, int64_t side_node,
                                            typename StT<ST>::R *f, typename StT<ST>::R *h, double *flux) {
   using R = typename StT<ST>::R;
+  constexpr bool AB = LAY == LAY_AB;
   const Node c = coords(a, m);
   const R fref = R(a.fref), href = R(a.href);
 #pragma unroll
@@ -405,15 +448,44 @@ __device__ __forceinline__ void pull_links(const KArgs &a, int64_t m, int32_t lb
     h[i] = ldp<Q, ST>(a.hsrc, sl, a.n, nd, href);
   }
   if (mask == 0) return;
+  // g*_i(x_b) and g*_opp(i)(x_b) of step t-1 per link direction i: in AB the
+  // node's own stored values (all of f also give the wall velocity); in AA
+  // g*_i(x_b) at its post-collision address and g*_opp(i)(x_b) from the side
+  // buffer (its slot is rewritten by another node in this step)
+  const DevWall<R> *walls = static_cast<const DevWall<R> *>(a.walls);
+  R fbi[Q], fbo[Q], hbi[Q], hbo[Q];
+  DevWall<R> w[Q];
+  if constexpr (AB) {
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      if constexpr (NS) fbi[i] = ldp<Q, ST>(a.fsrc, i, a.n, m, fref);
+      hbi[i] = ldp<Q, ST>(a.hsrc, i, a.n, m, href);
+    }
+  }
+#pragma unroll
+  for (int i = 1; i < Q; i++) {
+    if (!((mask >> i) & 1u)) continue;
+    const int32_t l = lb + __popc(mask & ((1u << i) - 1u));
+    w[i] = walls[l];
+    if constexpr (!AB) {
+      int sl;
+      int64_t nd;
+      post_addr<Q, LAY>(a, c, m, i, sl, nd);
+      if constexpr (NS) {
+        fbi[i] = ldp<Q, ST>(a.fsrc, sl, a.n, nd, fref);
+        fbo[i] = static_cast<const R *>(a.side_f)[l];
+      }
+      hbi[i] = ldp<Q, ST>(a.hsrc, sl, a.n, nd, href);
+      hbo[i] = static_cast<const R *>(a.side_h)[l];
+    }
+  }
   // velocity of the boundary node for the wall equilibrium: momentum over
   // density of its post-collision f of step t-1, or the prescribed velocity
   R ux, uy, uz;
   if constexpr (NS) {
-    if constexpr (LAY == LAY_AB) {
-      R fb[Q], rho;
-#pragma unroll
-      for (int i = 0; i < Q; i++) fb[i] = ldp<Q, ST>(a.fsrc, i, a.n, m, fref);
-      velocity_dir<Q, R>(fb, rho, ux, uy, uz);
+    if constexpr (AB) {
+      R rho;
+      velocity_dir<Q, R>(fbi, rho, ux, uy, uz);
     } else {
       const R *su = static_cast<const R *>(a.side_u) + 3 * side_node;
       ux = su[0];
@@ -427,33 +499,22 @@ __device__ __forceinline__ void pull_links(const KArgs &a, int64_t m, int32_t lb
   for (int i = 1; i < Q; i++) {
     if (!((mask >> i) & 1u)) continue;
     const int o = Lat<Q>::opp(i);
-    const int32_t l = lb + __popc(mask & ((1u << i) - 1u));
-    const DevLink lk = a.links[l];
-    const DevGroup &G = a.groups[lk.group];
-    // g*_i(x_b) of step t-1; g*_o(x_b) is kept in the side buffer in the AA
-    // layouts; g*_i(x_f) is the pulled value f[i] / h[i] (never rewritten by
-    // another link when it is used: that link would need x_f solid)
-    int sl;
-    int64_t nd;
-    post_addr<Q, LAY>(a, c, m, i, sl, nd);
+    // g*_i(x_f) is the pulled value f[i] / h[i] (never rewritten by another
+    // link when it is used: that link would need x_f solid)
     if constexpr (NS) {
-      const R gbi = ldp<Q, ST>(a.fsrc, sl, a.n, nd, fref);
-      if (G.f_scheme == 0 || lk.xf_solid || lk.q == 0.5) {
+      const R gbi = fbi[i], gbo = AB ? fbi[o] : fbo[i];
+      if (w[i].interp & 1)
+        f[o] = wall_ibb<R>(w[i].q, gbi, gbo, f[i]);
+      else
         f[o] = gbi;  // bounce-back (Eq. IBB at q = 1/2)
-      } else {
-        const R gbo = LAY == LAY_AB ? ldp<Q, ST>(a.fsrc, o, a.n, m, fref) : static_cast<const R *>(a.side_f)[l];
-        f[o] = wall_ibb<R>(R(lk.q), gbi, gbo, f[i]);
-      }
     }
-    const R hbi = ldp<Q, ST>(a.hsrc, sl, a.n, nd, href);
-    const R geq = geq_dir<Q, R>(i, R(G.H_w), ux, uy, uz);
-    if (G.h_scheme == 0 || lk.xf_solid || lk.q == 0.5) {
-      h[o] = -hbi + R(2) * geq;  // anti-bounce-back (Eq. IABB at q = 1/2)
-    } else {
-      const R hbo = LAY == LAY_AB ? ldp<Q, ST>(a.hsrc, o, a.n, m, href) : static_cast<const R *>(a.side_h)[l];
-      h[o] = wall_iabb<R>(R(lk.q), hbi, hbo, h[i], geq);
-    }
-    if (flux) flux[l] = double(h[o]) - double(hbi);
+    const R gbi = hbi[i], gbo = AB ? hbi[o] : hbo[i];
+    const R geq = geq_dir<Q, R>(i, w[i].H_w, ux, uy, uz);
+    if (w[i].interp & 2)
+      h[o] = wall_iabb<R>(w[i].q, gbi, gbo, h[i], geq);
+    else
+      h[o] = -gbi + R(2) * geq;  // anti-bounce-back (Eq. IABB at q = 1/2)
+    if (flux) flux[lb + __popc(mask & ((1u << i) - 1u))] = double(h[o]) - double(gbi);
   }
 }
 
@@ -502,20 +563,7 @@ __device__ __forceinline__ void special_node(const KArgs &a, int64_t t) {
   R f[Q], h[Q];
   if (sp.type == NODE_EQ) {
     if (flux) pull_links<Q, ST, NS, LAY>(a, m, sp.lb, sp.mask, 2 * t, f, h, flux);
-    const DevGroup &G = a.groups[sp.group];
-    R ux, uy, uz;
-    if (NS && !a.with_uvel) {
-      ux = R(G.u_w[0]);
-      uy = R(G.u_w[1]);
-      uz = Lat<Q>::D == 3 ? R(G.u_w[2]) : R(0);
-    } else {
-      prescribed_u<Q, R>(a, m, ux, uy, uz);
-    }
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-      if constexpr (NS) f[i] = geq_dir<Q, R>(i, R(G.rho_w), ux, uy, uz);
-      h[i] = geq_dir<Q, R>(i, R(G.H_w), ux, uy, uz);
-    }
+    eq_node<Q, ST, NS>(a, m, sp.group, f, h);
   } else {
     pull_links<Q, ST, NS, LAY>(a, m, sp.lb, sp.mask, 2 * t, f, h, flux);
     if (sp.type == NODE_OUTLET) {
@@ -556,7 +604,7 @@ __device__ __forceinline__ void fused_body(const KArgs &a, int sblocks) {
     return;
   }
   const int64_t tile = tile_of(a, blockIdx.x - sblocks, gridDim.x - sblocks);
-  bulk_node<Q, ST, NS, true, MODE_STEP, LAY, true>(a, tile * 256 + threadIdx.x);
+  bulk_node<Q, ST, NS, true, MODE_STEP, LAY>(a, tile * 256 + threadIdx.x);
 }
 
 // (The scalar state of the boundary path limits this launch to 7 waves per

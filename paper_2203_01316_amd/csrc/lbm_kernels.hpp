@@ -16,6 +16,17 @@ struct DevLink {
   double q;
 };
 
+// What the wall rules of one cut link read, in the arithmetic type R; derived
+// from the link and the group of its solid node when the geometry is set, so
+// a boundary node needs no dependent load of its group.
+template <class R>
+struct DevWall {
+  R q;             // link fraction (Eqs. IBB and IABB)
+  R H_w;           // wall value of h of the group
+  int32_t interp;  // bit 0: interpolated rule for f (else bounce-back),
+                   // bit 1: interpolated rule for h (else anti-bounce-back)
+};
+
 // Boundary node handled by the boundary kernel: EQ and OUTLET nodes and
 // non-solid nodes with at least one cut link.  Links of a node are stored
 // contiguously from lb in increasing direction, one per set bit of mask.
@@ -41,7 +52,18 @@ struct DevGroup {
 };
 
 enum : int { NODE_FLUID = 0, NODE_SOLID = 1, NODE_EQ = 2, NODE_OUTLET = 3 };
-enum : uint8_t { CLS_BULK = 0, CLS_SOLID = 1, CLS_SPECIAL = 2 };
+// Node classes (one byte per node).  EQ nodes without cut links and outlet
+// nodes whose upstream node is a plain fluid node of the same wavefront are
+// handled by the bulk threads, where their loads and stores coalesce with the
+// neighbours'; every other boundary node has a record in the boundary list.
+enum : uint8_t {
+  CLS_BULK = 0,
+  CLS_SOLID = 1,
+  CLS_SPECIAL = 2,  // processed from the boundary-node list
+  CLS_OUTLET = 3,   // outlet, upstream node = previous lane
+  CLS_EQ = 4        // CLS_EQ + g: EQ node of group g <= CLS_EQ_MAX_GROUP
+};
+constexpr int CLS_EQ_MAX_GROUP = 255 - CLS_EQ;
 
 // Streaming layouts (see lbm_impl.hpp): two arrays, or one array in the
 // swapped (S) or streamed (N) AA layout.
@@ -60,10 +82,10 @@ struct KArgs {
   const void *hsrc;
   void *hdst;
   const uint8_t *cls;      // node classes, or null when there is no geometry
-  const uint32_t *skip;    // bit m set: node m is not a bulk node (step kernel)
   const void *uvel;        // [3][n] arithmetic type, or null
   const void *src;         // [n] arithmetic type, or null
   const DevLink *links;
+  const void *walls;       // DevWall<arithmetic type> per link
   const DevSpecial *special;
   const DevGroup *groups;
   int64_t nspecial;

@@ -210,6 +210,45 @@ def heated_cylinder(nx: int = 2048, ny: int = 2048, r: float = 64, cx=None, cy=N
     return flags, q, groups, u, rho0, H0
 
 
+def boundary_mix(nx: int = 33, ny: int = 40, u_in: float = 0.03, seed: int = 4):
+    """Short coupled channel whose inlet and outlet nodes come in every local
+    configuration: walls at y = 0 and y = ny-1 (group 0: BB/ABB, H = 0); EQ
+    inlet column x = 0 (group 1: H = 1) touching the walls, with one node of
+    group 252 (H = 1.5) at y = 12 and one OUTLET node at y = 7 whose upstream
+    node wraps to x = nx-1 (left FLUID there); outlet column x = nx-1 (with
+    nx = 33 the node at y = 32 has n = 1088, a multiple of 64); a solid block
+    (group 2) at x = nx-3, y = 20..21 that gives the upstream nodes of four
+    outlets cut links; a disc of radius 4 at (14, 20) (group 2: IBB/IABB,
+    H = 2).  Velocity: u_x = u_in (1 + 0.1 xi(y)), xi ~ U(-1, 1) from numpy
+    PCG64(seed), zero in solids.  Returns (flags, q, groups, u[3, n], rho0, H0).
+    """
+    n = nx * ny
+    f = np.zeros((ny, nx), np.uint16)
+    f[:, 0] = flag(EQ, 1)
+    f[:, nx - 1] = flag(OUTLET, 0)
+    f[12, 0] = flag(EQ, 252)
+    f[7, 0] = flag(OUTLET, 0)
+    f[7, nx - 1] = flag(FLUID, 0)
+    f[20:22, nx - 3] = flag(SOLID, 2)
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    disc = (xx - 14) ** 2 + (yy - 20) ** 2 <= 16
+    f[disc] = flag(SOLID, 2)
+    f[0, :] = flag(SOLID, 0)
+    f[ny - 1, :] = flag(SOLID, 0)
+    flags = f.reshape(-1)
+    q = circle_q(nx, ny, flags, [(14.0, 20.0, 4.0, True)])
+    xi = np.random.Generator(np.random.PCG64(seed)).uniform(-1.0, 1.0, size=ny)
+    u = np.zeros((3, ny, nx))
+    u[0] = (u_in * (1.0 + 0.1 * xi))[:, None]
+    u[:, (f & 15) == SOLID] = 0.0
+    groups = [dict(f_scheme=0, h_scheme=0, rho_w=1.0, H_w=0.0),
+              dict(f_scheme=0, h_scheme=0, rho_w=1.0, H_w=1.0),
+              dict(f_scheme=1, h_scheme=1, rho_w=1.0, H_w=2.0)]
+    groups += [dict(f_scheme=0, h_scheme=0, rho_w=1.0, H_w=0.0)] * (252 - len(groups))
+    groups.append(dict(f_scheme=0, h_scheme=0, rho_w=1.0, H_w=1.5))
+    return flags, q, groups, u.reshape(3, n), np.ones(n), np.zeros(n)
+
+
 def taylor_green_3d(L: int = 256, u0: float = 0.04):
     """Taylor-Green vortex on an L^3 periodic box: u = u0 (sin kx cos ky cos kz,
     -cos kx sin ky cos kz, 0), rho = 1 + 3 p with p = u0^2/16 (cos 2kx + cos 2ky)

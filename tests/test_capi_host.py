@@ -98,10 +98,53 @@ def test_link_table_bit_exact_vs_oracle(L, oracle, Q, dims):
     assert mine.tobytes() == ref.tobytes()
     nl, ns = L.count_geometry(p, flags)
     assert nl == len(ref)
+    assert ns == _expected_records(flags, ref, dims[0])
+
+
+def _expected_records(flags, links, nx):
+    """Boundary-node records: every non-solid node with cut links, EQ nodes
+    with cut links, and outlet nodes unless the bulk threads take them (no cut
+    links on the node or on its upstream node n - 1, which is FLUID, x != 0 and
+    n % 64 != 0).  EQ nodes without cut links and of a group below 252 are
+    bulk-handled."""
     t = flags & 15
     has_link = np.zeros(len(flags), bool)
-    has_link[ref["node"]] = True
-    assert ns == int(np.count_nonzero((t != 1) & ((t == 2) | (t == 3) | has_link)))
+    has_link[links["node"]] = True
+    count = 0
+    for n in range(len(flags)):
+        if t[n] == 1:
+            continue
+        if t[n] == 3:
+            bulk = (not has_link[n] and n % nx != 0 and n % 64 != 0 and t[n - 1] == 0
+                    and not has_link[n - 1])
+            count += not bulk
+        elif has_link[n] or (t[n] == 2 and (flags[n] >> 4) > 251):
+            count += 1
+    return count
+
+
+def test_bulk_handled_boundary_nodes(L, oracle):
+    """A lattice with every inlet/outlet configuration: records exist exactly
+    for the nodes the rule above lists (the outlet at y = 32 starts a 64-node
+    group, the outlet at x = 0 has a periodic upstream, four outlets have an
+    upstream node with cut links, corner EQ nodes have cut links, one EQ node
+    is in group 252)."""
+    from paper_2203_01316_amd import workloads as W
+    flags, q, groups, _, _, _ = W.boundary_mix()
+    nx, ny = 33, 40
+    assert (32 + nx * 32) % 64 == 0
+    p = L.make_params(L.D2Q9, nx, ny, k=0.01, with_ns=True, nu=0.04)
+    links = oracle.Sim(9, nx, ny, flags=flags, qlink=q, groups=groups).links()
+    nl, ns = L.count_geometry(p, flags)
+    assert nl == len(links)
+    t = (flags & 15).reshape(ny, nx)
+    g = (flags >> 4).reshape(ny, nx)
+    exp = _expected_records(flags, links, nx)
+    # the group-252 EQ node has no cut link but keeps a record
+    assert t[12, 0] == L.EQ and g[12, 0] == 252
+    assert ns == exp
+    n_out = int(np.count_nonzero(t == L.OUTLET))
+    assert n_out == ny - 3 + 1
 
 
 def test_aa_layout_geometry(L, oracle):

@@ -96,6 +96,27 @@ def test_aa_coupled_cylinder(L, storage):
         _same(L, ab, aa, ("f", "h"), cols=(5, 150), group=1)
 
 
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_aa_boundary_mix(L, storage):
+    """Listed outlets (the thread also updates the upstream node) next to
+    bulk-handled ones (the upstream populations come from the previous lane)."""
+    flags, q, groups, u, rho0, H0 = W.boundary_mix()
+    uu = f32(u) if storage == "fp32" else u
+
+    def make(stream):
+        g = L.LBM(9, 33, 40, storage=storage, with_ns=True, nu=0.04, k=0.05, flags=flags, q=q, groups=groups,
+                  stream=stream)
+        g.set_velocity(uu)
+        g.init(H0, u=uu, rho=rho0)
+        return g
+
+    ab, aa = _both(L, make)
+    for k in (1, 2, 37):
+        ab.step(k)
+        aa.step(k)
+        _same(L, ab, aa, ("f", "h"), cols=(2, 31, 32), group=2)
+
+
 @pytest.mark.parametrize("storage", ["fp32", "fp64"])
 def test_aa_d3q27_sphere(L, storage):
     nx, ny, nz = 20, 14, 12

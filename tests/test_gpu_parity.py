@@ -131,6 +131,30 @@ def test_cylinder_ns_ade_small(L, oracle, storage, tol):
     assert red[2] == pytest.approx(flux[lk["group"] == 1].sum(), rel=max(tol, 1e-10) * 10)
 
 
+@pytest.mark.parametrize("storage,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_boundary_mix_coupled(L, oracle, storage, tol):
+    """Inlet and outlet nodes in every local configuration (bulk-handled and
+    listed outlets and EQ nodes, an outlet with a periodic upstream node, an
+    upstream node with cut links, group 252), coupled f + h, 300 steps."""
+    flags, q, groups, u, rho0, H0 = W.boundary_mix()
+    uu = f32(u) if storage != "fp64" else u
+    g, o = pair(L, oracle, Q=9, dims=(33, 40, 1), storage=storage, with_ns=True, nu=0.04, k=0.05, uvel=u,
+                flags=flags, q=q, groups=groups, H0=H0, u_init=uu, rho0=rho0)
+    for steps in (1, 299):
+        g.step(steps)
+        o.step(steps)
+        fo, ho = o.pre()
+        assert rel_l2(gpu_pre(g, "f"), fluid_only(fo, o.flags)) < tol
+        assert rel_l2(gpu_pre(g, "h"), fluid_only(ho, o.flags)) < tol
+        assert rel_l2(gpu_post(g, "h"), fluid_only(o.post_h, o.flags)) < tol
+    red = g.reduce(group=2, columns=[2, 31, 32])
+    _, ho, flux = o.pre(with_flux=True)
+    lk = o.links()
+    assert red[2] == pytest.approx(flux[lk["group"] == 2].sum(), rel=max(tol, 1e-10) * 10)
+    for j, X in enumerate([2, 31, 32]):
+        assert red[3 + j] == pytest.approx(o.section_flux(X, ho), rel=max(tol, 1e-11) * 10, abs=1e-12)
+
+
 def test_cylinder_full_size_one_step(L, oracle):
     """2048^2 coupled FP32 (the benchmark configuration): one GPU step equals
     the oracle's step from the same stored state at every node."""
