@@ -133,12 +133,18 @@ void compute_rates(const lbm_params *p, double *sf, double *sh) {
   preset_rates(p, p->relax_h, s_H, p->s_custom_h, sh);
 }
 
+// Node count of a population buffer: padded to whole tiles; also the plane
+// stride of the FP16 layout.
+int64_t plane_nodes(int64_t n) { return (n + POP_PAD - 1) / POP_PAD * POP_PAD; }
+
 Layout layout(const lbm_params *p) {
   Layout L;
   const int64_t n = node_count(p);
   const int Q = p->lattice;
   size_t off = 0;
-  L.pop_bytes = align_up((size_t)Q * n * storage_size(p->storage));
+  // tiles of consecutive nodes with all Q slots each, or Q planes of
+  // plane_nodes() elements (lbm_impl.hpp)
+  L.pop_bytes = align_up((size_t)Q * plane_nodes(n) * storage_size(p->storage));
   const int copies = p->stream == LBM_STREAM_AA ? 1 : 2;
   for (int lat = 0; lat < 2; lat++)
     for (int c = 0; c < 2; c++) {
@@ -462,11 +468,15 @@ static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   a.groups = reinterpret_cast<const DevGroup *>(ctx->ws + ctx->L.off_groups);
   a.nspecial = ctx->geom ? ctx->nspecial : 0;
   a.n = ctx->n;
+  a.ps = plane_nodes(ctx->n);
   a.nx = ctx->p.nx;
   a.ny = ctx->p.ny;
   a.nz = ctx->p.nz;
-  // measured on MI355X: slab-per-XCD order for D2Q9, row order for D3Q27
-  a.tilemap = ctx->Q == 9 ? 0 : 1;
+  // block orders measured best on MI355X: FP16 planes, slab per XCD (D2Q9)
+  // or rows per XCD (D3Q27); tiled FP32/FP64, rows per XCD (D2Q9) or
+  // dispatch order (D3Q27)
+  const bool planes = ctx->p.storage == LBM_FP16_DEV;
+  a.tilemap = ctx->Q == 9 ? (planes ? 0 : 1) : (planes ? 1 : 2);
   a.row_blocks = (ctx->p.nx + 255) / 256;
   for (int k = 0; k < 27; k++) {
     a.sf[k] = ctx->sfc[k];
@@ -739,6 +749,7 @@ lbm_status lbm_init_equilibrium(lbm_ctx *ctx, const double *rho_dev, const doubl
   }
   a.H = H_dev;
   a.n = ctx->n;
+  a.ps = plane_nodes(ctx->n);
   a.nx = ctx->p.nx;
   a.ny = ctx->p.ny;
   a.nz = ctx->p.nz;

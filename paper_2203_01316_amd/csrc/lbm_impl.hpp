@@ -65,26 +65,43 @@ struct StT<ST_FP16_DEV> {
   static constexpr bool DEV = true;
 };
 
-// Load / store population i (stored in slot `slot`) of node m.  The deviation
-// storages keep g_i - w_i g_ref; w_i = w_opp(i), so a swapped slot needs no
-// other weight.
+// Population storage of one lattice.  FP64 and FP32 elements: tiles of
+// T = POP_TILE_BYTES / sizeof(S) consecutive nodes, each holding its Q slots
+// one after the other, [m / T][slot][m % T]; a block then reads and writes runs
+// of consecutive bytes per slot and tile, and the slots of a tile share DRAM
+// pages.  FP16 elements: one plane of ps elements per slot, [slot][m], which
+// measured faster for 2-byte elements on MI355X.
+template <int Q, class S>
+__device__ __forceinline__ int64_t pop_index(int slot, int64_t ps, int64_t m) {
+  if constexpr (sizeof(S) == 2) {
+    return (int64_t)slot * ps + m;
+  } else {
+    constexpr uint64_t T = POP_TILE_BYTES / sizeof(S);
+    const uint64_t u = (uint64_t)m;
+    return (int64_t)(((u / T) * Q + (uint64_t)slot) * T + (u % T));
+  }
+}
+
+// Load / store population i (stored in slot `slot`) of node m; ps is the plane
+// stride of the FP16 layout.  The deviation storages keep g_i - w_i g_ref;
+// w_i = w_opp(i), so a swapped slot needs no other weight.
 template <int Q, int ST>
-__device__ __forceinline__ typename StT<ST>::R ldp(const void *base, int slot, int64_t n, int64_t m,
+__device__ __forceinline__ typename StT<ST>::R ldp(const void *base, int slot, int64_t ps, int64_t m,
                                                    typename StT<ST>::R ref) {
   using T = StT<ST>;
   using R = typename T::R;
-  const typename T::S *p = static_cast<const typename T::S *>(base) + (int64_t)slot * n + m;
+  const typename T::S *p = static_cast<const typename T::S *>(base) + pop_index<Q, typename T::S>(slot, ps, m);
   R v = StoreT<typename T::S>::ld(p);
   if constexpr (T::DEV) v += weight<Q, R>(slot) * ref;
   return v;
 }
 
 template <int Q, int ST>
-__device__ __forceinline__ void stp(void *base, int slot, int64_t n, int64_t m, typename StT<ST>::R v,
+__device__ __forceinline__ void stp(void *base, int slot, int64_t ps, int64_t m, typename StT<ST>::R v,
                                     typename StT<ST>::R ref) {
   using T = StT<ST>;
   if constexpr (T::DEV) v -= weight<Q, typename T::R>(slot) * ref;
-  typename T::S *p = static_cast<typename T::S *>(base) + (int64_t)slot * n + m;
+  typename T::S *p = static_cast<typename T::S *>(base) + pop_index<Q, typename T::S>(slot, ps, m);
   StoreT<typename T::S>::st(p, v);
 }
 
@@ -251,7 +268,7 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
         int64_t nd;
         store_addr<Q, LAY>(a, c, m, i, sl, nd);
         f[i] = g[Lat<Q>::slot(i)];
-        stp<Q, ST>(a.fdst, sl, a.n, nd, f[i], R(a.fref));
+        stp<Q, ST>(a.fdst, sl, a.ps, nd, f[i], R(a.fref));
       }
     }
 #pragma unroll
@@ -263,7 +280,7 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
       int64_t nd;
       store_addr<Q, LAY>(a, c, m, i, sl, nd);
       h[i] = g[Lat<Q>::slot(i)];
-      stp<Q, ST>(a.hdst, sl, a.n, nd, h[i], R(a.href));
+      stp<Q, ST>(a.hdst, sl, a.ps, nd, h[i], R(a.href));
     }
   } else if constexpr (MODE == MODE_PRE) {
 #pragma unroll
@@ -339,7 +356,9 @@ __device__ __forceinline__ int64_t row_tile(int64_t b, int64_t nb, int64_t G) {
 }
 
 __device__ __forceinline__ int64_t tile_of(const KArgs &a, int64_t b, int64_t nb) {
-  return a.tilemap == 0 ? xcd_tile(b, nb) : row_tile(b, nb, a.row_blocks);
+  if (a.tilemap == 0) return xcd_tile(b, nb);
+  if (a.tilemap == 1) return row_tile(b, nb, a.row_blocks);
+  return b;
 }
 
 // ---------------------------------------------------------------------------
@@ -388,8 +407,8 @@ __device__ __forceinline__ void bulk_node(const KArgs &a, int64_t m) {
     int sl;
     int64_t nd;
     pull_addr<Q, LAY>(a, c, m, i, sl, nd);
-    if constexpr (NS) f[i] = ldp<Q, ST>(a.fsrc, sl, a.n, nd, R(a.fref));
-    h[i] = ldp<Q, ST>(a.hsrc, sl, a.n, nd, R(a.href));
+    if constexpr (NS) f[i] = ldp<Q, ST>(a.fsrc, sl, a.ps, nd, R(a.fref));
+    h[i] = ldp<Q, ST>(a.hsrc, sl, a.ps, nd, R(a.href));
   }
   if constexpr (GEOM) {
     if (__ballot(cl == CLS_OUTLET)) {
@@ -444,8 +463,8 @@ __device__ __forceinline__ void pull_links(const KArgs &a, int64_t m, int32_t lb
     int sl;
     int64_t nd;
     pull_addr<Q, LAY>(a, c, m, i, sl, nd);
-    if constexpr (NS) f[i] = ldp<Q, ST>(a.fsrc, sl, a.n, nd, fref);
-    h[i] = ldp<Q, ST>(a.hsrc, sl, a.n, nd, href);
+    if constexpr (NS) f[i] = ldp<Q, ST>(a.fsrc, sl, a.ps, nd, fref);
+    h[i] = ldp<Q, ST>(a.hsrc, sl, a.ps, nd, href);
   }
   if (mask == 0) return;
   // g*_i(x_b) and g*_opp(i)(x_b) of step t-1 per link direction i: in AB the
@@ -458,8 +477,8 @@ __device__ __forceinline__ void pull_links(const KArgs &a, int64_t m, int32_t lb
   if constexpr (AB) {
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-      if constexpr (NS) fbi[i] = ldp<Q, ST>(a.fsrc, i, a.n, m, fref);
-      hbi[i] = ldp<Q, ST>(a.hsrc, i, a.n, m, href);
+      if constexpr (NS) fbi[i] = ldp<Q, ST>(a.fsrc, i, a.ps, m, fref);
+      hbi[i] = ldp<Q, ST>(a.hsrc, i, a.ps, m, href);
     }
   }
 #pragma unroll
@@ -472,10 +491,10 @@ __device__ __forceinline__ void pull_links(const KArgs &a, int64_t m, int32_t lb
       int64_t nd;
       post_addr<Q, LAY>(a, c, m, i, sl, nd);
       if constexpr (NS) {
-        fbi[i] = ldp<Q, ST>(a.fsrc, sl, a.n, nd, fref);
+        fbi[i] = ldp<Q, ST>(a.fsrc, sl, a.ps, nd, fref);
         fbo[i] = static_cast<const R *>(a.side_f)[l];
       }
-      hbi[i] = ldp<Q, ST>(a.hsrc, sl, a.n, nd, href);
+      hbi[i] = ldp<Q, ST>(a.hsrc, sl, a.ps, nd, href);
       hbo[i] = static_cast<const R *>(a.side_h)[l];
     }
   }
@@ -631,9 +650,9 @@ __global__ void __launch_bounds__(64) k_side(const KArgs a) {
       int sl;
       int64_t nd;
       post_addr<Q, LAY>(a, c, m, i, sl, nd);
-      if constexpr (NS) f[i] = ldp<Q, ST>(a.fsrc, sl, a.n, nd, R(a.fref));
+      if constexpr (NS) f[i] = ldp<Q, ST>(a.fsrc, sl, a.ps, nd, R(a.fref));
       else f[i] = R(0);
-      h[i] = ldp<Q, ST>(a.hsrc, sl, a.n, nd, R(a.href));
+      h[i] = ldp<Q, ST>(a.hsrc, sl, a.ps, nd, R(a.href));
     }
     save_side<Q, ST, NS>(a, k == 0 ? sp.lb : sp.ub, k == 0 ? sp.mask : sp.umask, 2 * t + k, f, h);
   }
@@ -677,9 +696,9 @@ __global__ void __launch_bounds__(256) k_init(const InitArgs a) {
     const int slot = LAY == LAY_AB ? i : Lat<Q>::opp(i);
     if constexpr (NS) {
       const double rho = a.rho ? a.rho[s] : 1.0;
-      stp<Q, ST>(a.fdst, slot, a.n, m, R(geq_dir<Q, double>(i, rho, ux, uy, uz)), R(a.fref));
+      stp<Q, ST>(a.fdst, slot, a.ps, m, R(geq_dir<Q, double>(i, rho, ux, uy, uz)), R(a.fref));
     }
-    stp<Q, ST>(a.hdst, slot, a.n, m, R(geq_dir<Q, double>(i, a.H[s], ux, uy, uz)), R(a.href));
+    stp<Q, ST>(a.hdst, slot, a.ps, m, R(geq_dir<Q, double>(i, a.H[s], ux, uy, uz)), R(a.href));
   }
 }
 
@@ -699,9 +718,9 @@ __global__ void __launch_bounds__(256) k_convert(const KArgs a, const void *from
     int64_t nd;
     post_addr<Q, LAY>(a, c, m, i, sl, nd);
     if constexpr (TO_STORAGE)
-      stp<Q, ST>(to, sl, a.n, nd, R(static_cast<const double *>(from)[i * a.n + m]), R(ref));
+      stp<Q, ST>(to, sl, a.ps, nd, R(static_cast<const double *>(from)[i * a.n + m]), R(ref));
     else
-      static_cast<double *>(to)[i * a.n + m] = solid ? 0.0 : double(ldp<Q, ST>(from, sl, a.n, nd, R(ref)));
+      static_cast<double *>(to)[i * a.n + m] = solid ? 0.0 : double(ldp<Q, ST>(from, sl, a.ps, nd, R(ref)));
   }
 }
 

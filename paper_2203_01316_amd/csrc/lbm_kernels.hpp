@@ -7,6 +7,13 @@
 
 namespace lbm {
 
+// Bytes per slot of a population tile (FP64 and FP32 storage, see
+// lbm_impl.hpp): a tile holds POP_TILE_BYTES / sizeof(element) consecutive
+// nodes.  The node count of a lattice is padded to POP_PAD nodes, a multiple
+// of every tile.
+constexpr int POP_TILE_BYTES = 1024;
+constexpr int POP_PAD = POP_TILE_BYTES / 4;
+
 // Device copy of one cut link; same layout as lbm_link.
 struct DevLink {
   int32_t node;
@@ -90,9 +97,11 @@ struct KArgs {
   const DevGroup *groups;
   int64_t nspecial;
   int64_t n;
+  int64_t ps;              // plane stride of the FP16 population layout
   int32_t nx, ny, nz;
   int32_t with_uvel;       // advection velocity from the field (else u0)
-  int32_t tilemap;         // block -> tile order: 0 one slab per XCD, 1 rows per XCD
+  int32_t tilemap;         // block -> tile order: 0 one slab per XCD, 1 rows per XCD,
+                           // 2 dispatch order
   int32_t row_blocks;      // blocks per x-row (tilemap 1)
   double sf[27];           // rates of f, chimera order
   double sh[27];           // rates of h, chimera order
@@ -116,6 +125,7 @@ struct InitArgs {
   const void *uvel;   // fallback field, arithmetic type, or null
   const double *H;    // [n]
   int64_t n;
+  int64_t ps;         // plane stride of the FP16 population layout
   int32_t nx, ny, nz;
   double u0[3];
   double fref, href;
