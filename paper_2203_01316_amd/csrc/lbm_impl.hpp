@@ -67,10 +67,19 @@ struct StT<ST_FP16_DEV> {
 
 // Population storage of one lattice.  FP64 and FP32 elements: tiles of
 // T = POP_TILE_BYTES / sizeof(S) consecutive nodes, each holding its Q slots
-// one after the other, [m / T][slot][m % T]; a block then reads and writes runs
-// of consecutive bytes per slot and tile, and the slots of a tile share DRAM
-// pages.  FP16 elements: one plane of ps elements per slot, [slot][m], which
-// measured faster for 2-byte elements on MI355X.
+// one after the other, [m / T][tile_pos(slot)][m % T]; a block then reads and
+// writes runs of consecutive bytes per slot and tile, and the slots of a tile
+// share DRAM pages.  In D2Q9 the three slots of equal e_y (pulled from one
+// neighbouring row) are adjacent.  FP16 elements: one plane of ps elements per
+// slot, [slot][m], which measured faster for 2-byte elements on MI355X.
+template <int Q>
+__device__ __forceinline__ constexpr int tile_pos(int s) {
+  if constexpr (Q == 9)
+    return (Lat<Q>::ey(s) + 1) * 3 + (Lat<Q>::ex(s) + 1);
+  else
+    return s;
+}
+
 template <int Q, class S>
 __device__ __forceinline__ int64_t pop_index(int slot, int64_t ps, int64_t m) {
   if constexpr (sizeof(S) == 2) {
@@ -78,7 +87,7 @@ __device__ __forceinline__ int64_t pop_index(int slot, int64_t ps, int64_t m) {
   } else {
     constexpr uint64_t T = POP_TILE_BYTES / sizeof(S);
     const uint64_t u = (uint64_t)m;
-    return (int64_t)(((u / T) * Q + (uint64_t)slot) * T + (u % T));
+    return (int64_t)(((u / T) * Q + (uint64_t)tile_pos<Q>(slot)) * T + (u % T));
   }
 }
 
