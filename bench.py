@@ -1,7 +1,7 @@
 """Throughput of the fused central-moment stream-and-collide step on one GPU.
 
 Workload: coupled D2Q9 flow (f) + heat (h) lattices on a 2048 x 2048 grid in
-FP32 storage, two-array (AB) streaming: heated cylinder of radius 64 (IBB for
+FP32 storage, in-place (AA) streaming by default: heated cylinder of radius 64 (IBB for
 f, IABB for h), equilibrium inlet column with a seeded perturbation of the
 inlet velocity, zero-gradient outlet column, periodic in y; Re = 100 (u = 0.04,
 D = 128, nu = 0.0512), Pr = 0.71.  Synthetic inputs, all resident in HBM before
@@ -90,18 +90,21 @@ def time_steps(torch, g, steps, warmup):
     return e0.elapsed_time(e1) / 1e3 / steps
 
 
-def leg_cylinder(torch, L, W, np, storage, nx, ny, steps):
+def leg_cylinder(torch, L, W, np, storage, stream, nx, ny, steps):
     nu = 0.04 * 128 / 100.0
     flags, q, groups, u, rho0, H0 = W.heated_cylinder(nx, ny, 64, u_in=0.04, amp=1e-3, seed=0)
     uf = np.asarray(u, np.float32)
     g = L.LBM(L.D2Q9, nx, ny, with_ns=True, storage=storage, nu=nu, k=nu / 0.71, flags=flags, q=q,
-              groups=groups, rho_ref=1.0, H_ref=10.0)
+              groups=groups, rho_ref=1.0, H_ref=10.0, stream=L.STREAM_AA if stream == "aa" else L.STREAM_AB)
     g.set_velocity(uf)
     g.init(H0, u=uf.astype(np.float64), rho=rho0)
     sec = time_steps(torch, g, steps, 50)
-    bpn = 2 * 2 * 9 * (2 if storage == "fp16_dev" else 4)
+    bpn = 2 * 2 * 9 * (8 if storage == "fp64" else 2 if storage == "fp16_dev" else 4)
     mlups = nx * ny / sec / 1e6
-    return {"workload": f"d2q9_ns_ade_heated_cylinder_{nx}x{ny}", "storage": storage, "MLUPS": round(mlups, 1),
+    del g
+    torch.cuda.empty_cache()
+    return {"workload": f"d2q9_ns_ade_heated_cylinder_{nx}x{ny}", "storage": storage, "stream": stream.upper(),
+            "MLUPS": round(mlups, 1),
             "bytes_per_node": bpn, "pct_hbm_roofline": round(100 * mlups * 1e6 * bpn / HBM_PEAK, 2),
             "us_per_step": round(sec * 1e6, 2)}
 
@@ -116,7 +119,8 @@ def leg_tgv(torch, L, W, storage, n1, steps):
     red = g.reduce()
     bpn = 2 * 2 * 27 * (2 if storage == "fp16_dev" else 4)
     mlups = n1 ** 3 / sec / 1e6
-    out = {"workload": f"d3q27_ns_ade_taylor_green_{n1}^3", "storage": storage, "MLUPS": round(mlups, 1),
+    out = {"workload": f"d3q27_ns_ade_taylor_green_{n1}^3", "storage": storage, "stream": "AB",
+           "MLUPS": round(mlups, 1),
            "bytes_per_node": bpn, "pct_hbm_roofline": round(100 * mlups * 1e6 * bpn / HBM_PEAK, 2),
            "us_per_step": round(sec * 1e6, 2), "mass": red[0], "energy": red[1]}
     del g
@@ -200,6 +204,8 @@ def main():
     ap.add_argument("--nx", type=int, default=2048)
     ap.add_argument("--ny", type=int, default=2048)
     ap.add_argument("--storage", default="fp32")
+    ap.add_argument("--stream", default="aa", choices=["aa", "ab"],
+                    help="population layout: in place (aa, measured faster for D2Q9 FP32) or two arrays (ab)")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP16, D3Q27 and adjoint legs")
@@ -223,7 +229,8 @@ def main():
     flags, q, groups, u, rho0, H0 = W.heated_cylinder(nx, ny, 64, u_in=0.04, amp=1e-3, seed=0)
     uf = np.asarray(u, np.float32)
     g = L.LBM(L.D2Q9, nx, ny, with_ns=True, storage=args.storage, nu=nu, k=k, relax_f="ns", relax_h="trt",
-              flags=flags, q=q, groups=groups, device=dev)
+              flags=flags, q=q, groups=groups, device=dev,
+              stream=L.STREAM_AA if args.stream == "aa" else L.STREAM_AB)
     g.set_velocity(uf)
     g.init(H0, u=uf.astype(np.float64), rho=rho0)
     n = nx * ny
@@ -251,13 +258,14 @@ def main():
     bytes_node = 2 * 2 * 9 * (8 if args.storage == "fp64" else 4 if args.storage.startswith("fp32") else 2)
     mlups = n * args.steps / sec / 1e6
     # One fused launch per step covers every non-solid node (bulk and
-    # boundary), launched back to back on this stream: the HIP events around
-    # the timed region divided by the step count give the average launch
-    # duration (inter-launch gaps included, so this errs low).
+    # boundary), launched back to back on this stream (AA: the two layout
+    # phases alternate): the HIP events around the timed region divided by the
+    # step count give the average launch duration (inter-launch gaps
+    # included, so this errs low).
     n_work = n - nsolid
     launch_avg = gpu_sec / args.steps
     achieved = n_work * bytes_node / launch_avg
-    traffic = read_traffic(f"d2q9_ns_ade_{nx}x{ny}_{args.storage}")
+    traffic = read_traffic(f"d2q9_ns_ade_{nx}x{ny}_{args.storage}_{args.stream}")
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -273,13 +281,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"d2q9_ns_ade_heated_cylinder_{nx}x{ny}", "lattice": "D2Q9",
                    "lattices": "f (NS, CM) + h (ADE, CM-TRT)", "nx": nx, "ny": ny,
-                   "storage": args.storage, "stream": "AB", "Re": 100, "Pr": 0.71,
+                   "storage": args.storage, "stream": args.stream.upper(), "Re": 100, "Pr": 0.71,
                    "bytes_per_node": bytes_node, "boundary_nodes": nspecial, "solid_nodes": nsolid},
         "pct_hbm_roofline": round(100.0 * mlups * 1e6 * bytes_node / HBM_PEAK, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved / 1e9, 1), "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
                      "traffic": None if traffic is None else int(traffic),
-                     "kernel": "k_fused", "avg_launch_us": round(launch_avg * 1e6, 2),
+                     "kernel": "k_fused" + (" (AA: swapped and streamed layout phases alternate)"
+                                            if args.stream == "aa" else ""),
+                     "avg_launch_us": round(launch_avg * 1e6, 2),
                      "bytes_per_launch": n_work * bytes_node},
         "copy_ceiling_GBps": round(ceiling / 1e9, 1),
         "mass": red[0],
@@ -289,7 +299,9 @@ def main():
         del g
         torch.cuda.empty_cache()
         sc = args.extra_scale
-        out["also"] = [leg_cylinder(torch, L, W, np, "fp16_dev", nx, ny, max(10, int(1000 * sc))),
+        other = "ab" if args.stream == "aa" else "aa"
+        out["also"] = [leg_cylinder(torch, L, W, np, args.storage, other, nx, ny, max(10, int(1000 * sc))),
+                       leg_cylinder(torch, L, W, np, "fp16_dev", "ab", nx, ny, max(10, int(1000 * sc))),
                        leg_tgv(torch, L, W, "fp32", 256, max(5, int(100 * sc))),
                        leg_tgv(torch, L, W, "fp16_dev", 256, max(5, int(100 * sc)))]
         out["adjoint"] = leg_adjoint(torch, L, np, steps=max(90, int(2000 * sc)))
