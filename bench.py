@@ -301,6 +301,7 @@ def main():
         sc = args.extra_scale
         other = "ab" if args.stream == "aa" else "aa"
         out["also"] = [leg_cylinder(torch, L, W, np, args.storage, other, nx, ny, max(10, int(1000 * sc))),
+                       leg_cylinder(torch, L, W, np, "fp16_dev", "aa", nx, ny, max(10, int(1000 * sc))),
                        leg_cylinder(torch, L, W, np, "fp16_dev", "ab", nx, ny, max(10, int(1000 * sc))),
                        leg_tgv(torch, L, W, "fp32", 256, max(5, int(100 * sc))),
                        leg_tgv(torch, L, W, "fp16_dev", 256, max(5, int(100 * sc)))]

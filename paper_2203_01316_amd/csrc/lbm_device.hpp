@@ -81,8 +81,7 @@ template <class S>
 struct StoreT;
 // Loads and stores of the population arrays.  Each stored element is written
 // once per step and read back only in the next one, so stores bypass the
-// caches (non-temporal); loads of the tiled FP64/FP32 layout are ordinary
-// (measured faster on MI355X), those of the FP16 planes non-temporal.
+// caches (non-temporal); loads are ordinary (measured faster on MI355X).
 template <>
 struct StoreT<double> {
   __device__ static double ld(const double *p) { return *p; }
@@ -96,7 +95,7 @@ struct StoreT<float> {
 template <>
 struct StoreT<__half> {
   __device__ static float ld(const __half *p) {
-    unsigned short b = __builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p));
+    unsigned short b = *reinterpret_cast<const unsigned short *>(p);
     return __half2float(__ushort_as_half(b));
   }
   __device__ static void st(__half *p, float v) {

@@ -472,11 +472,10 @@ static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   a.nx = ctx->p.nx;
   a.ny = ctx->p.ny;
   a.nz = ctx->p.nz;
-  // block orders measured best on MI355X: FP16 planes, slab per XCD (D2Q9)
-  // or rows per XCD (D3Q27); tiled FP32/FP64, rows per XCD (D2Q9) or
-  // dispatch order (D3Q27)
+  // block orders measured best on MI355X: D2Q9 one slab per XCD (FP16
+  // planes) or rows per XCD (tiles); D3Q27 dispatch order
   const bool planes = ctx->p.storage == LBM_FP16_DEV;
-  a.tilemap = ctx->Q == 9 ? (planes ? 0 : 1) : (planes ? 1 : 2);
+  a.tilemap = ctx->Q == 9 ? (planes ? 0 : 1) : 2;
   a.row_blocks = (ctx->p.nx + 255) / 256;
   for (int k = 0; k < 27; k++) {
     a.sf[k] = ctx->sfc[k];
