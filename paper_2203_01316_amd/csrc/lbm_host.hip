@@ -472,10 +472,16 @@ static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   a.nx = ctx->p.nx;
   a.ny = ctx->p.ny;
   a.nz = ctx->p.nz;
-  // block orders measured best on MI355X: D2Q9 one slab per XCD (FP16
-  // planes) or rows per XCD (tiles); D3Q27 dispatch order
+  // block orders measured best on MI355X: D2Q9 tiles rows per XCD; D2Q9
+  // FP16 planes one slab per XCD (dispatch order in the streamed AA phase);
+  // D3Q27 dispatch order
   const bool planes = ctx->p.storage == LBM_FP16_DEV;
-  a.tilemap = ctx->Q == 9 ? (planes ? 0 : 1) : 2;
+  if (ctx->Q == 27)
+    a.tilemap = 2;
+  else if (!planes)
+    a.tilemap = 1;
+  else
+    a.tilemap = ctx->lay() == LAY_AA_N ? 2 : 0;
   a.row_blocks = (ctx->p.nx + 255) / 256;
   for (int k = 0; k < 27; k++) {
     a.sf[k] = ctx->sfc[k];

@@ -66,18 +66,16 @@ struct StT<ST_FP16_DEV> {
 };
 
 // Population storage of one lattice.  FP64 and FP32 elements: tiles of
-// T = POP_TILE_BYTES / sizeof(S) consecutive nodes, each holding its Q slots
+// T = pop_tile_bytes(Q) / sizeof(S) consecutive nodes, each holding its Q slots
 // one after the other, [m / T][tile_pos(slot)][m % T]; a block then reads and
 // writes runs of consecutive bytes per slot and tile, and the slots of a tile
-// share DRAM pages.  In D2Q9 the three slots of equal e_y (pulled from one
-// neighbouring row) are adjacent.  FP16 elements: one plane of ps elements per
-// slot, [slot][m], which measured faster for 2-byte elements on MI355X.
+// share DRAM pages.  Inside a tile the slots of equal (e_z, e_y), which are
+// pulled from one neighbouring row, are adjacent.  FP16 elements: one plane of
+// ps elements per slot, [slot][m], which measured faster for 2-byte elements
+// on MI355X.
 template <int Q>
 __device__ __forceinline__ constexpr int tile_pos(int s) {
-  if constexpr (Q == 9)
-    return (Lat<Q>::ey(s) + 1) * 3 + (Lat<Q>::ex(s) + 1);
-  else
-    return s;
+  return ((Lat<Q>::ez(s) + 1) * 3 + (Lat<Q>::ey(s) + 1)) * 3 + (Lat<Q>::ex(s) + 1) - (Lat<Q>::D == 2 ? 9 : 0);
 }
 
 template <int Q, class S>
@@ -85,7 +83,7 @@ __device__ __forceinline__ int64_t pop_index(int slot, int64_t ps, int64_t m) {
   if constexpr (sizeof(S) == 2) {
     return (int64_t)slot * ps + m;
   } else {
-    constexpr uint64_t T = POP_TILE_BYTES / sizeof(S);
+    constexpr uint64_t T = pop_tile_bytes(Q) / sizeof(S);
     const uint64_t u = (uint64_t)m;
     return (int64_t)(((u / T) * Q + (uint64_t)tile_pos<Q>(slot)) * T + (u % T));
   }

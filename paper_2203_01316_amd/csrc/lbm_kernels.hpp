@@ -8,11 +8,11 @@
 namespace lbm {
 
 // Bytes per slot of a population tile (FP64 and FP32 storage, see
-// lbm_impl.hpp): a tile holds POP_TILE_BYTES / sizeof(element) consecutive
-// nodes.  The node count of a lattice is padded to POP_PAD nodes, a multiple
-// of every tile.
-constexpr int POP_TILE_BYTES = 1024;
-constexpr int POP_PAD = POP_TILE_BYTES / 4;
+// lbm_impl.hpp; measured best on MI355X): a tile holds pop_tile_bytes(Q) /
+// sizeof(element) consecutive nodes.  The node count of a lattice is padded
+// to a multiple of POP_PAD nodes, a multiple of every tile.
+constexpr int pop_tile_bytes(int Q) { return Q == 27 ? 2048 : 1024; }
+constexpr int POP_PAD = 2048 / 4;
 
 // Device copy of one cut link; same layout as lbm_link.
 struct DevLink {
