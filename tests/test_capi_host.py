@@ -49,6 +49,8 @@ def test_version_and_workspace(L):
     (dict(storage=7), "storage"),
     (dict(lattice=15), "lattice"),
     (dict(stream=7), "stream mode"),
+    (dict(nx=0), "nx, ny, nz"),
+    (dict(ny=-3), "nx, ny, nz"),
     (dict(with_source=True, with_ns=True, nu=0.1), "source"),
 ])
 def test_param_validation(L, kw, msg):

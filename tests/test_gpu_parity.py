@@ -57,6 +57,37 @@ def test_ragged_sizes_fp64(L, oracle):
         assert rel_l2(gpu_pre(g), o.pre()[1]) < TOL64, dims
 
 
+@pytest.mark.parametrize("storage,tol", [("fp32", TOL32), ("fp32_dev", TOL32), ("fp16_dev", 2e-4)])
+@pytest.mark.parametrize("stream", ["ab", "aa"])
+def test_ragged_sizes_coupled(L, oracle, storage, tol, stream):
+    """Coupled f + h on lattices smaller than one population tile, with odd
+    extents, single-node axes and partial last tiles, D2Q9 and D3Q27, both
+    streaming layouts and every reduced-precision storage."""
+    rng = np.random.default_rng(32)
+    cases = [(9, (1, 1, 1)), (9, (5, 3, 1)), (9, (257, 3, 1)), (9, (129, 7, 1)),
+             (27, (3, 5, 7)), (27, (1, 1, 9)), (27, (17, 3, 2)), (27, (65, 9, 3))]
+    for Q, dims in cases:
+        n = int(np.prod(dims))
+        D = 2 if Q == 9 else 3
+        u = np.zeros((3, n))
+        u[:D] = rng.uniform(-0.04, 0.04, (D, n))
+        uu = f32(u)
+        rho0 = 1 + 0.01 * rng.uniform(size=n)
+        H0 = 1 + 0.1 * rng.uniform(size=n)
+        g = L.LBM(Q, *dims, with_ns=True, storage=storage, nu=0.03, k=0.02,
+                  stream=L.STREAM_AA if stream == "aa" else L.STREAM_AB, rho_ref=1.0, H_ref=1.0)
+        g.init(H0, u=uu, rho=f32(rho0))
+        sf, sh = L.relaxation_rates(g.params)
+        o = oracle.Sim(Q, *dims, with_ns=True, s_f=sf, s_h=sh)
+        o.init(H0, u=uu, rho=f32(rho0))
+        for steps in (1, 12):
+            g.step(steps)
+            o.step(steps)
+            fo, ho = o.pre()
+            assert rel_l2(gpu_pre(g, "f"), fo) < tol, (Q, dims, steps)
+            assert rel_l2(gpu_pre(g, "h"), ho) < tol, (Q, dims, steps)
+
+
 # ---------------------------------------------------------------------------
 # Channel with walls, inlet, outlet and an interpolated cylinder
 # ---------------------------------------------------------------------------
