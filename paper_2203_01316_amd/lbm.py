@@ -201,10 +201,13 @@ def _groups_struct(groups):
 def nusselt(q_surface: float, q_in: float, q_out: float, k: float, T_wall: float, T_in: float) -> float:
     """Nusselt number of a heated cylinder from the FP64 reductions of
     lbm_reduce (Sec. 4.4): Nu = varsigma D / k with varsigma = qdot / (pi D
-    (T_wall - T_in)), so Nu = qdot / (pi k (T_wall - T_in)); qdot is the mean
-    of the heater flux and the net section flux q_in - q_out."""
+    (T_wall - T_in)), so Nu = qdot / (pi k (T_wall - T_in)).  qdot is the mean
+    of the heater flux (energy the wall links inject per step) and the energy
+    the flow gains between the upstream and the downstream section, q_out -
+    q_in (section fluxes sum e_x h, positive downstream); in a steady state the
+    two agree."""
     import math
-    qdot = 0.5 * (q_surface + (q_in - q_out))
+    qdot = 0.5 * (q_surface + (q_out - q_in))
     return qdot / (math.pi * k * (T_wall - T_in))
 
 

@@ -249,6 +249,44 @@ def boundary_mix(nx: int = 33, ny: int = 40, u_in: float = 0.03, seed: int = 4):
     return flags, q, groups, u.reshape(3, n), np.ones(n), np.zeros(n)
 
 
+def confined_cylinder(S: int = 1, Pr: float = 10.0, second_order: bool = True, xc_frac: float = 0.2):
+    """Steady forced convection from a confined cylinder (Sec. 4.4, case table):
+    lattice (1000 S) x (150 S), D = 30 S, U = 0.01 / S, nu = 0.03, k = nu / Pr,
+    Re = U D / nu = 10.  Inlet: EQ column x = 0 (group 0: rho = 1, u = (U, 0),
+    H = T_in = 10), standing in for the paper's Zou-He inlet.  Outlet:
+    zero-gradient column x = nx - 1.  Top and bottom: periodic in y; the steady
+    flow is symmetric about the channel axis, where the periodic images then
+    meet with zero normal velocity and zero normal gradients, as on the
+    paper's symmetry planes.  Cylinder (group 1, H = T_cyl = 11): centre
+    (xc_frac nx, ny / 2 - 1/2), solid iff |x - c| <= D / 2, IBB/IABB when
+    second_order else BB/ABB; q from circle_q.  Returns (flags, q, groups,
+    u[3, n], rho0, H0, info) with info holding nu, k, D, U, T_in, T_cyl and
+    the section columns 50 lu after the inlet and 100 lu before the outlet."""
+    nx, ny = 1000 * S, 150 * S
+    D, U, nu = 30.0 * S, 0.01 / S, 0.03
+    k = nu / Pr
+    r = D / 2.0
+    cx, cy = xc_frac * nx, ny / 2.0 - 0.5
+    n = nx * ny
+    f = np.zeros((ny, nx), np.uint16)
+    f[:, 0] = flag(EQ, 0)
+    f[:, nx - 1] = flag(OUTLET, 0)
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    disc = (xx - cx) ** 2 + (yy - cy) ** 2 <= r * r
+    f[disc] = flag(SOLID, 1)
+    flags = f.reshape(-1)
+    q = circle_q(nx, ny, flags, [(cx, cy, r, True)])
+    u = np.zeros((3, ny, nx))
+    u[0] = U
+    u[:, disc] = 0.0
+    T_in, T_cyl = 10.0, 11.0
+    scheme = 1 if second_order else 0
+    groups = [dict(f_scheme=0, h_scheme=0, rho_w=1.0, H_w=T_in),
+              dict(f_scheme=scheme, h_scheme=scheme, rho_w=1.0, H_w=T_cyl)]
+    info = dict(nx=nx, ny=ny, nu=nu, k=k, D=D, U=U, T_in=T_in, T_cyl=T_cyl, sections=(50, nx - 101))
+    return flags, q, groups, u.reshape(3, n), np.ones(n), np.full(n, T_in), info
+
+
 def taylor_green_3d(L: int = 256, u0: float = 0.04):
     """Taylor-Green vortex on an L^3 periodic box: u = u0 (sin kx cos ky cos kz,
     -cos kx sin ky cos kz, 0), rho = 1 + 3 p with p = u0^2/16 (cos 2kx + cos 2ky)

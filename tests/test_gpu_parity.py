@@ -400,6 +400,25 @@ def test_nusselt_from_reductions(L, oracle):
     assert np.isfinite(nu_g) and nu_g == pytest.approx(nu_o, rel=1e-9)
 
 
+def test_confined_cylinder_nusselt(L):
+    """Sec. 4.4 set-up on the GPU path (coarse lattice 1000 x 150, D = 30,
+    Re = 10, Pr = 10, CM-TRT for h, IBB/IABB on the cylinder, FP32): after five
+    flow-through times the heater flux and the net section flux agree within
+    1.5 % and Nu lies within 3 % of the paper's finite-element value 4.82."""
+    flags, q, groups, u, rho0, H0, info = W.confined_cylinder(1, 10.0, True)
+    g = L.LBM(9, info["nx"], info["ny"], with_ns=True, storage="fp32", nu=info["nu"], k=info["k"], flags=flags, q=q,
+              groups=groups, rho_ref=1.0, H_ref=10.0)
+    g.set_velocity(f32(u))
+    g.init(H0, u=u, rho=rho0)
+    g.step(int(5 * info["nx"] / info["U"]))
+    red = g.reduce(group=1, columns=list(info["sections"]))
+    bal = (red[4] - red[3]) / red[2]
+    nu = L.nusselt(red[2], red[3], red[4], info["k"], info["T_cyl"], info["T_in"])
+    print("confined cylinder Pr = 10: Nu %.3f, heater/section balance %.4f" % (nu, bal))
+    assert abs(bal - 1.0) < 0.015
+    assert abs(nu - 4.82) < 0.03 * 4.82
+
+
 def test_concentric_cylinders_convergence_on_gpu(L):
     """Sec. 4.3 on the GPU path (FP64, CM-TRT, k = 0.1): steady conduction
     between concentric cylinders; IABB converges at second order, ABB and EQ at
