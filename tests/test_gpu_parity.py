@@ -255,6 +255,48 @@ def test_d3q27_full_size_sampled(L, oracle):
     assert rel_l2(qh, oh) < TOL32
 
 
+def test_largest_lattice_fp64(L, oracle):
+    """A lattice of 32771 x 32765 nodes (1.07e9, population indices past 2^32),
+    FP64, in-place layout.  The advection-diffusion step is linear and
+    translation invariant, so from H = 1 + a(x) + b(y) the GPU field after two
+    steps must equal A(x) + B(y), where the oracle evolves 1 + a on a 32771 x 1
+    lattice and b on a 1 x 32765 lattice; checked on 4096 random nodes and on
+    every node of the first and last rows and columns."""
+    import torch
+    nx, ny = 32771, 32765
+    u0, k = (0.03, -0.02, 0.0), 0.02
+    rng = np.random.default_rng(77)
+    a = 0.01 * rng.uniform(-1, 1, nx)
+    b = 0.01 * rng.uniform(-1, 1, ny)
+    g = L.LBM(9, nx, ny, storage="fp64", k=k, u0=u0, stream=L.STREAM_AA)
+    at = torch.as_tensor(a, device=g.device)
+    bt = torch.as_tensor(b, device=g.device)
+    H0 = (1.0 + at[None, :] + bt[:, None]).reshape(-1)
+    g.init(H0)
+    del H0
+    g.step(2)
+    H = torch.empty(g.n, dtype=torch.float64, device=g.device)
+    g._ck(L._lib.lbm_macroscopic(g.ctx, None, None, H.data_ptr()))
+    g.sync()
+    H = H.reshape(ny, nx)
+    sf, sh = L.relaxation_rates(g.params)
+    ox = oracle.Sim(9, nx, 1, s_h=sh, u0=u0)
+    ox.init(1.0 + a)
+    ox.step(2)
+    oy = oracle.Sim(9, 1, ny, s_h=sh, u0=u0)
+    oy.init(b)
+    oy.step(2)
+    A = ox.macroscopic()[2]
+    B = oy.macroscopic()[2]
+    ys = np.concatenate([rng.integers(0, ny, 4096), np.zeros(nx, int), np.full(nx, ny - 1),
+                         np.arange(ny), np.arange(ny)])
+    xs = np.concatenate([rng.integers(0, nx, 4096), np.arange(nx), np.arange(nx), np.zeros(ny, int),
+                         np.full(ny, nx - 1)])
+    got = H[torch.as_tensor(ys, device=g.device), torch.as_tensor(xs, device=g.device)].cpu().numpy()
+    ref = A[xs] + B[ys]
+    assert np.max(np.abs(got - ref)) < 1e-13
+
+
 # ---------------------------------------------------------------------------
 # Source term, state I/O, errors
 # ---------------------------------------------------------------------------
