@@ -11,8 +11,8 @@ namespace lbm {
 // lbm_impl.hpp; measured best on MI355X): a tile holds pop_tile_bytes(Q) /
 // sizeof(element) consecutive nodes.  The node count of a lattice is padded
 // to a multiple of POP_PAD nodes, a multiple of every tile.
-constexpr int pop_tile_bytes(int Q) { return Q == 27 ? 2048 : 1024; }
-constexpr int POP_PAD = 2048 / 4;
+constexpr int pop_tile_bytes(int Q) { return Q == 27 ? 4096 : 1024; }
+constexpr int POP_PAD = 4096 / 4;
 
 // Device copy of one cut link; same layout as lbm_link.
 struct DevLink {
