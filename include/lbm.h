@@ -153,8 +153,14 @@ size_t lbm_workspace_bytes(const lbm_params *p);
  * above: s_f[27] and s_h[27] (entries past Q are 1). */
 lbm_status lbm_relaxation_rates(const lbm_params *p, double *s_f, double *s_h);
 
-/* Counts the cut links and boundary nodes of a geometry (flags as in
- * lbm_set_geometry).  Either output may be NULL. */
+/* Counts the cut links and the boundary-node records of a geometry (flags as
+ * in lbm_set_geometry), the capacities max_links and max_special must hold.
+ * A record is kept for every non-solid node with cut links and for the EQ and
+ * OUTLET nodes the bulk threads do not handle: an EQ node is handled there when
+ * it has no cut link and its group is below 252; an OUTLET node n when neither
+ * it nor its upstream node n - 1 has a cut link, that node is FLUID, x != 0 and
+ * n % 64 != 0.  In the AA layout a listed outlet's upstream node needs no
+ * record of its own.  Either output may be NULL. */
 lbm_status lbm_count_geometry(const lbm_params *p, const uint16_t *flags, int64_t *n_links,
                               int64_t *n_special);
 
