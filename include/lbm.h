@@ -9,7 +9,8 @@
  * and per node, pull-streaming, the boundary rules of Sec. 3 (BB/IBB on f,
  * ABB/IABB on h, EQ nodes, zero-gradient outlet) and the central-moment
  * collision of Sec. 2.1 (Eqs. raw_mom_def, cm_mom_def, H_cm_collision) with a
- * diagonal relaxation matrix, in one fused HIP kernel.
+ * diagonal relaxation matrix, in one fused HIP kernel per step (D3Q27 with
+ * listed boundary nodes: a bulk and a boundary kernel).
  *
  * Conventions
  *  - Ownership: every device buffer is owned by the caller and borrowed by the
@@ -22,8 +23,12 @@
  *  - Errors: calls return an lbm_status and never abort; lbm_last_error()
  *    returns a message that names the offending argument or index.
  *  - Threads: one context per stream; calls on one context must not overlap.
- *  - Layout: populations are structure-of-arrays, index
- *    [i][z][y][x] with x fastest; node index n = x + nx (y + ny z).
+ *  - Layout: populations exchanged through this interface
+ *    (lbm_get_populations, lbm_set_populations, the adjoint's lambda) are
+ *    FP64 or arithmetic-type structure-of-arrays, index [i][z][y][x] with x
+ *    fastest; node index n = x + nx (y + ny z).  The storage layout inside
+ *    the workspace (node tiles, or planes for FP16) is private; snapshots of
+ *    lbm_save_state() are opaque.
  *    Direction order i: D2Q9 (0,0),(1,0),(0,1),(1,1),(-1,0),(0,-1),(1,-1),
  *    (-1,1),(-1,-1) (the e_z = 0 subset of the D3Q27 order); D3Q27 is the
  *    order of Sec. 2.1.  Moment order of per-moment rates: Sec. 2.1 (D3Q27:
@@ -167,8 +172,9 @@ lbm_status lbm_count_geometry(const lbm_params *p, const uint16_t *flags, int64_
 /* Builds the cut-link table of a geometry on the host: flags[n], q[Q][n]
  * (read on cut links only; NULL means q = 1/2), groups[n_groups].  Writes at
  * most cap links to out, the total to *count.  Rejects q outside (0, 1] on a
- * cut link, a group index >= n_groups, a type above 3, and a FLUID/OUTLET
- * node at x = 0 marked OUTLET whose upstream node is solid. */
+ * cut link, a group index >= n_groups on a SOLID or EQ node, a type above 3,
+ * an OUTLET node whose upstream node (x - 1, periodic in x) is SOLID and, in
+ * the AA layout, one whose upstream node is not FLUID. */
 lbm_status lbm_build_links(const lbm_params *p, const uint16_t *flags, const double *q,
                            int32_t n_groups, lbm_link *out, int64_t cap, int64_t *count);
 
