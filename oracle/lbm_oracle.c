@@ -325,6 +325,149 @@ int ora_collide_node(int Q, const double *g, const double *u, const double *s,
 }
 
 /* ---------------------------------------------------------------------------
+ * Cumulants (Sec. 2.1.1, Eqs. hydro_cu_collision and H_cu_collision; the
+ * transform of Geier et al. 2015 that the paper adopts).  For a population set
+ * g with raw moments m_n = sum_a g_a e_a^n (multi-index n, every exponent
+ * below 3) the zeroth cumulant is c_0 = m_0 and, for n != 0, c_n is the
+ * cumulant of the normalised distribution g / m_0: the coefficient of the
+ * logarithm of its moment generating function.  With mu = m / m_0 the
+ * identity d_j M = M d_j log M gives, for n = n' + e_j,
+ *   mu_n = sum_{k <= n'} B(n', k) mu_{n'-k} c_{k+e_j},
+ *   B(n', k) = prod_d binomial(n'_d, k_d),
+ * which is solved for c_n (the k = n' term is c_n itself) in increasing total
+ * order, and read forwards for the inverse.  Every index it touches stays
+ * inside the moment set, so the 27 (9) cumulants are exactly those of the
+ * lattice's moments.
+ * ------------------------------------------------------------------------- */
+static int mom_slot(const ora_lat *L, const int n[3]) {
+  for (int k = 0; k < L->Q; k++)
+    if (L->mo[k][0] == n[0] && L->mo[k][1] == n[1] && L->mo[k][2] == n[2]) return k;
+  return -1;
+}
+
+static int mom_order(const ora_lat *L, int k) { return L->mo[k][0] + L->mo[k][1] + L->mo[k][2]; }
+
+/* first axis j with n_j > 0 */
+static int first_axis(const int n[3]) { return n[0] ? 0 : (n[1] ? 1 : 2); }
+
+/* sum_{k <= np, k != skip_top ? np : -} B(np, k) mu[np - k] c[k + e_j] */
+static double recursion_sum(const ora_lat *L, const int np[3], int j, const double *mu, const double *c,
+                            int include_top) {
+  double acc = 0.0;
+  for (int kx = 0; kx <= np[0]; kx++)
+    for (int ky = 0; ky <= np[1]; ky++)
+      for (int kz = 0; kz <= np[2]; kz++) {
+        const int k[3] = {kx, ky, kz};
+        if (!include_top && kx == np[0] && ky == np[1] && kz == np[2]) continue;
+        const int rest[3] = {np[0] - kx, np[1] - ky, np[2] - kz};
+        int kj[3] = {kx, ky, kz};
+        kj[j] += 1;
+        const double B = binom(np[0], kx) * binom(np[1], ky) * binom(np[2], kz);
+        acc += B * mu[mom_slot(L, rest)] * c[mom_slot(L, kj)];
+      }
+  return acc;
+}
+
+/* raw moments of g -> cumulants c (c[0] = m_0) */
+static void cumulants(const ora_lat *L, const double *g, double *c) {
+  int Q = L->Q;
+  double m[ORA_MAXQ], mu[ORA_MAXQ];
+  for (int k = 0; k < Q; k++) {
+    double v = 0.0;
+    for (int a = 0; a < Q; a++)
+      v += g[a] * ipow(L->e[a][0], L->mo[k][0]) * ipow(L->e[a][1], L->mo[k][1]) * ipow(L->e[a][2], L->mo[k][2]);
+    m[k] = v;
+  }
+  for (int k = 0; k < Q; k++) mu[k] = m[k] / m[0];
+  c[0] = m[0];
+  for (int t = 1; t <= 6; t++)
+    for (int k = 1; k < Q; k++) {
+      if (mom_order(L, k) != t) continue;
+      const int j = first_axis(L->mo[k]);
+      int np[3] = {L->mo[k][0], L->mo[k][1], L->mo[k][2]};
+      np[j] -= 1;
+      c[k] = mu[k] - recursion_sum(L, np, j, mu, c, 0);
+    }
+}
+
+/* cumulants c -> populations g (raw moments m = c_0 mu, then M^-1) */
+static void from_cumulants(const ora_ctx *C, const double *c, double *g) {
+  const ora_lat *L = &C->L;
+  int Q = L->Q;
+  double mu[ORA_MAXQ], m[ORA_MAXQ];
+  mu[0] = 1.0;
+  for (int t = 1; t <= 6; t++)
+    for (int k = 1; k < Q; k++) {
+      if (mom_order(L, k) != t) continue;
+      const int j = first_axis(L->mo[k]);
+      int np[3] = {L->mo[k][0], L->mo[k][1], L->mo[k][2]};
+      np[j] -= 1;
+      mu[k] = recursion_sum(L, np, j, mu, c, 1);
+    }
+  for (int k = 0; k < Q; k++) m[k] = c[0] * mu[k];
+  for (int a = 0; a < Q; a++) {
+    double v = 0.0;
+    for (int k = 0; k < Q; k++) v += C->Minv[a * Q + k] * m[k];
+    g[a] = v;
+  }
+}
+
+/* Equilibrium cumulants (Sec. 2.1.1, the vector C^H,eq; the same shape with
+ * psi = rho for f): psi at 000, u at the first order, cs^2 at 200/020/002,
+ * zero elsewhere. */
+static void cu_equilibrium(const ora_lat *L, double psi, const double u[3], double *eq) {
+  for (int k = 0; k < L->Q; k++) {
+    const int *n = L->mo[k];
+    const int ord = n[0] + n[1] + n[2];
+    const int pure = (n[0] == ord) || (n[1] == ord) || (n[2] == ord);
+    if (ord == 0)
+      eq[k] = psi;
+    else if (ord == 1)
+      eq[k] = n[0] ? u[0] : (n[1] ? u[1] : u[2]);
+    else if (ord == 2 && pure)
+      eq[k] = CS2;
+    else
+      eq[k] = 0.0;
+  }
+}
+
+/* One cumulant collision with the source of App. D (Eq. H_cu_collision_with_Q):
+ *   C   = cumulants(g),  psi = C_000 + src/2,
+ *   C*  = C + S (C^eq(psi, u) - C) + (1 - s_000/2) src e_000,
+ *   g*  = cumulants^-1(C*).                                                 */
+static void collide_node_cu(const ora_ctx *C, const double *g, const double u[3], const double *s, double src,
+                            double *gs) {
+  int Q = C->L.Q;
+  double c[ORA_MAXQ], eq[ORA_MAXQ];
+  cumulants(&C->L, g, c);
+  cu_equilibrium(&C->L, c[0] + 0.5 * src, u, eq);
+  for (int k = 0; k < Q; k++) c[k] = c[k] + s[k] * (eq[k] - c[k]);
+  c[0] += (1.0 - 0.5 * s[0]) * src;
+  from_cumulants(C, c, gs);
+}
+
+int ora_cumulants(int Q, const double *g, double *c) {
+  ora_lat L;
+  if (build_lattice(Q, &L)) return -1;
+  cumulants(&L, g, c);
+  return 0;
+}
+
+int ora_from_cumulants(int Q, const double *c, double *g) {
+  ora_ctx C;
+  if (ctx_init(Q, &C)) return -1;
+  from_cumulants(&C, c, g);
+  return 0;
+}
+
+int ora_collide_node_cu(int Q, const double *g, const double *u, const double *s, double src, double *gs) {
+  ora_ctx C;
+  if (ctx_init(Q, &C)) return -1;
+  collide_node_cu(&C, g, u, s, src, gs);
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
  * Whole-lattice configuration.
  * ------------------------------------------------------------------------- */
 enum { ORA_FLUID = 0, ORA_SOLID = 1, ORA_EQ = 2, ORA_OUTLET = 3 };
@@ -354,6 +497,8 @@ typedef struct {
   int32_t n_groups;
   int32_t collide_off;  /* 1: collision is the identity (streaming checks) */
   const ora_group *groups;
+  int32_t cu_f;         /* 1: f uses the cumulant collision, 0: central moments */
+  int32_t cu_h;         /* the same for h */
 } ora_cfg;
 
 typedef struct {
@@ -439,6 +584,8 @@ int ora_collide(const ora_cfg *c, const double *f, const double *h, double *fs, 
       for (int a = 0; a < Q; a++) g[a] = f[a * N + n];
       if (c->collide_off)
         memcpy(gs, g, sizeof(double) * Q);
+      else if (c->cu_f)
+        collide_node_cu(&C, g, u, c->s_f, 0.0, gs);
       else
         collide_node(&C, g, u, c->s_f, 0.0, gs);
       for (int a = 0; a < Q; a++) fs[a * N + n] = gs[a];
@@ -448,6 +595,8 @@ int ora_collide(const ora_cfg *c, const double *f, const double *h, double *fs, 
     for (int a = 0; a < Q; a++) g[a] = h[a * N + n];
     if (c->collide_off)
       memcpy(gs, g, sizeof(double) * Q);
+    else if (c->cu_h)
+      collide_node_cu(&C, g, u, c->s_h, c->src ? c->src[n] : 0.0, gs);
     else
       collide_node(&C, g, u, c->s_h, c->src ? c->src[n] : 0.0, gs);
     for (int a = 0; a < Q; a++) hs[a * N + n] = gs[a];

@@ -48,7 +48,7 @@ class Cfg(C.Structure):
                 ("s_f", C.c_double * 27), ("s_h", C.c_double * 27), ("u0", C.c_double * 3),
                 ("uvel", C.c_void_p), ("src", C.c_void_p), ("flags", C.c_void_p),
                 ("qlink", C.c_void_p), ("n_groups", C.c_int32), ("collide_off", C.c_int32),
-                ("groups", C.c_void_p)]
+                ("groups", C.c_void_p), ("cu_f", C.c_int32), ("cu_h", C.c_int32)]
 
 
 class Link(C.Structure):
@@ -130,6 +130,31 @@ def collide_node(Q: int, g, u, s, src: float = 0.0):
     return out
 
 
+def cumulants(Q: int, g):
+    """Cumulants of a population set (moment order of the oracle's tables):
+    c[0] = sum g, the others those of the normalised distribution."""
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    out = np.zeros(Q)
+    assert lib().ora_cumulants(Q, _p(g), _p(out)) == 0
+    return out
+
+
+def from_cumulants(Q: int, c):
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    out = np.zeros(Q)
+    assert lib().ora_from_cumulants(Q, _p(c), _p(out)) == 0
+    return out
+
+
+def collide_node_cu(Q: int, g, u, s, src: float = 0.0):
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    ss = np.ascontiguousarray(s, dtype=np.float64)
+    out = np.zeros(Q)
+    assert lib().ora_collide_node_cu(Q, _p(g), _p(uu), _p(ss), C.c_double(src), _p(out)) == 0
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Relaxation presets (Sec. 2.1.1) -- moment order of the oracle's tables
 # ---------------------------------------------------------------------------
@@ -163,7 +188,8 @@ def preset(Q: int, kind: str, rate: float) -> np.ndarray:
 # ---------------------------------------------------------------------------
 class Sim:
     def __init__(self, Q, nx, ny, nz=1, *, with_ns=False, s_f=None, s_h=None, u0=(0.0, 0.0, 0.0),
-                 uvel=None, src=None, flags=None, qlink=None, groups=(), collide_off=False):
+                 uvel=None, src=None, flags=None, qlink=None, groups=(), collide_off=False, cu_f=False,
+                 cu_h=False):
         self.Q, self.nx, self.ny, self.nz = Q, nx, ny, nz
         self.N = nx * ny * nz
         self.with_ns = bool(with_ns)
@@ -172,6 +198,8 @@ class Sim:
         c.Q, c.nx, c.ny, c.nz = Q, nx, ny, nz
         c.with_ns = int(with_ns)
         c.collide_off = int(collide_off)
+        c.cu_f = int(cu_f)
+        c.cu_h = int(cu_h)
         sf = np.ones(27) if s_f is None else np.asarray(s_f, float)
         sh = np.ones(27) if s_h is None else np.asarray(s_h, float)
         for k in range(27):
