@@ -90,12 +90,13 @@ def time_steps(torch, g, steps, warmup):
     return e0.elapsed_time(e1) / 1e3 / steps
 
 
-def leg_cylinder(torch, L, W, np, storage, stream, nx, ny, steps):
+def leg_cylinder(torch, L, W, np, storage, stream, nx, ny, steps, cu_f=False, cu_h=False):
     nu = 0.04 * 128 / 100.0
     flags, q, groups, u, rho0, H0 = W.heated_cylinder(nx, ny, 64, u_in=0.04, amp=1e-3, seed=0)
     uf = np.asarray(u, np.float32)
     g = L.LBM(L.D2Q9, nx, ny, with_ns=True, storage=storage, nu=nu, k=nu / 0.71, flags=flags, q=q,
-              groups=groups, rho_ref=1.0, H_ref=10.0, stream=L.STREAM_AA if stream == "aa" else L.STREAM_AB)
+              groups=groups, rho_ref=1.0, H_ref=10.0, stream=L.STREAM_AA if stream == "aa" else L.STREAM_AB,
+              relax_h="1st" if cu_h else "trt", cumulant_f=cu_f, cumulant_h=cu_h)
     g.set_velocity(uf)
     g.init(H0, u=uf.astype(np.float64), rho=rho0)
     sec = time_steps(torch, g, steps, 50)
@@ -104,15 +105,16 @@ def leg_cylinder(torch, L, W, np, storage, stream, nx, ny, steps):
     del g
     torch.cuda.empty_cache()
     return {"workload": f"d2q9_ns_ade_heated_cylinder_{nx}x{ny}", "storage": storage, "stream": stream.upper(),
+            "collision": ("f cumulant" if cu_f else "f CM-NS") + (", h Cumulants-1st" if cu_h else ", h CM-TRT"),
             "MLUPS": round(mlups, 1),
             "bytes_per_node": bpn, "pct_hbm_roofline": round(100 * mlups * 1e6 * bpn / HBM_PEAK, 2),
             "us_per_step": round(sec * 1e6, 2)}
 
 
-def leg_tgv(torch, L, W, storage, n1, steps):
+def leg_tgv(torch, L, W, storage, n1, steps, cu=False):
     rho, u, H = W.taylor_green_3d(n1, 0.04)
-    g = L.LBM(L.D3Q27, n1, n1, n1, with_ns=True, storage=storage, nu=0.002, k=0.002, relax_h="trt",
-              rho_ref=1.0, H_ref=1.0)
+    g = L.LBM(L.D3Q27, n1, n1, n1, with_ns=True, storage=storage, nu=0.002, k=0.002,
+              relax_h="1st" if cu else "trt", rho_ref=1.0, H_ref=1.0, cumulant_f=cu, cumulant_h=cu)
     g.init(H, u=u, rho=rho)
     del rho, u, H
     sec = time_steps(torch, g, steps, 10)
@@ -120,6 +122,7 @@ def leg_tgv(torch, L, W, storage, n1, steps):
     bpn = 2 * 2 * 27 * (2 if storage == "fp16_dev" else 4)
     mlups = n1 ** 3 / sec / 1e6
     out = {"workload": f"d3q27_ns_ade_taylor_green_{n1}^3", "storage": storage, "stream": "AB",
+           "collision": "f cumulant, h Cumulants-1st" if cu else "f CM-NS, h CM-TRT",
            "MLUPS": round(mlups, 1),
            "bytes_per_node": bpn, "pct_hbm_roofline": round(100 * mlups * 1e6 * bpn / HBM_PEAK, 2),
            "us_per_step": round(sec * 1e6, 2), "mass": red[0], "energy": red[1]}
@@ -304,7 +307,12 @@ def main():
                        leg_cylinder(torch, L, W, np, "fp16_dev", "aa", nx, ny, max(10, int(1000 * sc))),
                        leg_cylinder(torch, L, W, np, "fp16_dev", "ab", nx, ny, max(10, int(1000 * sc))),
                        leg_tgv(torch, L, W, "fp32", 256, max(5, int(100 * sc))),
-                       leg_tgv(torch, L, W, "fp16_dev", 256, max(5, int(100 * sc)))]
+                       leg_tgv(torch, L, W, "fp16_dev", 256, max(5, int(100 * sc))),
+                       # the paper's kernels: cumulant f with CM-TRT or Cumulants-1st h
+                       leg_cylinder(torch, L, W, np, "fp32", "aa", nx, ny, max(10, int(1000 * sc)), cu_f=True),
+                       leg_cylinder(torch, L, W, np, "fp32", "aa", nx, ny, max(10, int(1000 * sc)), cu_f=True,
+                                    cu_h=True),
+                       leg_tgv(torch, L, W, "fp32", 256, max(5, int(100 * sc)), cu=True)]
         out["adjoint"] = leg_adjoint(torch, L, np, steps=max(90, int(2000 * sc)))
         out["adjoint_forward_ratio"] = out["adjoint"]["no_replay"]["ratio"]
     if not args.no_cpu:

@@ -123,7 +123,15 @@ typedef struct {
   int32_t with_source; /* 1: per-node source Q of h (App. D) */
   int32_t max_links;   /* capacity of the cut-link table */
   int32_t max_special; /* capacity of the boundary-node list */
-  int32_t reserved;
+  int32_t cumulant;    /* collision family per lattice: bit 0 h, bit 1 f use the
+                        * cumulant collision (Eqs. H_cu_collision,
+                        * hydro_cu_collision, source as in App. D) instead of
+                        * central moments; the rates are those of relax_h /
+                        * relax_f in cumulant order (LBM_CM_1ST for h is the
+                        * paper's Cumulants-1st, LBM_CM_NS for f relaxes the
+                        * second-order cumulants at s_nu).  The cumulant
+                        * transform normalises by the zeroth moment, which must
+                        * not vanish. */
   double nu;        /* kinematic viscosity (lattice units), f lattice */
   double k;         /* conductivity / diffusivity (lattice units), h lattice */
   double rho_ref;   /* deviation reference of f (the *_DEV storages) */
@@ -249,8 +257,8 @@ lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32
 
 /* ---- discrete adjoint ----------------------------------------------------
  * Reverse mode of the advection-diffusion step with a source Q (App. D) for
- * contexts with with_ns = 0 and no geometry (fully periodic); other contexts
- * return LBM_EUNSUPPORTED.  Not in the paper: the reverse step is the exact
+ * contexts with with_ns = 0, no geometry (fully periodic) and the
+ * central-moment collision of h; other contexts return LBM_EUNSUPPORTED.  Not in the paper: the reverse step is the exact
  * transpose of the forward step.  That step is affine in (state, Q) for a
  * prescribed velocity, so the reverse step needs no forward state.
  * lambda: adjoint of the canonical (pre-collision) state, device [Q][n] in

@@ -282,6 +282,89 @@ __device__ __forceinline__ void collide(R *g, const R *s, R ux, R uy, R uz, R sr
   from_central<D, R>(g, ux, uy, uz);
 }
 
+// ---------------------------------------------------------------------------
+// Cumulant collision (Sec. 2.1.1, Eqs. hydro_cu_collision and
+// H_cu_collision, with the source of App. D).  The zeroth cumulant is the sum
+// of the populations; the others are the cumulants of the normalised
+// distribution, computed here from its central moments about u (first-order
+// cumulants are then mean - u, higher ones do not depend on the shift).  With
+// mu = normalised central moments and the multi-index identity
+// d_j M = M d_j log M, for n = n' + e_j:
+//   mu_n = sum_{k <= n'} B(n', k) mu_{n'-k} c_{k+e_j},  B = prod_d binom(n'_d, k_d),
+// solved for c_n in increasing total order (forward) or read as it stands
+// (inverse).  The equilibrium about u: 0 at first order, cs^2 at 200/020/002,
+// 0 elsewhere.
+// ---------------------------------------------------------------------------
+template <int D>
+__host__ __device__ constexpr int cm_x(int k) { return D == 2 ? k / 3 : k / 9; }
+template <int D>
+__host__ __device__ constexpr int cm_y(int k) { return D == 2 ? k % 3 : (k / 3) % 3; }
+template <int D>
+__host__ __device__ constexpr int cm_z(int k) { return D == 2 ? 0 : k % 3; }
+template <int D>
+__host__ __device__ constexpr int cm_slot(int m, int n, int o) { return D == 2 ? m * 3 + n : m * 9 + n * 3 + o; }
+__host__ __device__ constexpr int binom2(int n, int k) { return (n == 2 && k == 1) ? 2 : 1; }
+
+// FWD: c[k] (k > 0) from mu; else mu[k] (k > 0) from c.  mu[0] = 1.
+template <int D, bool FWD, class R>
+__device__ __forceinline__ void cumulant_recursion(R *mu, R *c) {
+  constexpr int NQ = D == 2 ? 9 : 27;
+#pragma unroll
+  for (int t = 1; t <= 2 * D; t++) {
+#pragma unroll
+    for (int k = 1; k < NQ; k++) {
+      const int m = cm_x<D>(k), n = cm_y<D>(k), o = cm_z<D>(k);
+      if (m + n + o != t) continue;
+      const int jx = m > 0 ? 1 : 0, jy = (!jx && n > 0) ? 1 : 0, jz = (!jx && !jy) ? 1 : 0;
+      const int pm = m - jx, pn = n - jy, po = o - jz;
+      R acc = FWD ? mu[k] : R(0);
+#pragma unroll
+      for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int b = 0; b < 3; b++)
+#pragma unroll
+          for (int e = 0; e < (D == 3 ? 3 : 1); e++) {
+            if (a > pm || b > pn || e > po) continue;
+            if (FWD && a == pm && b == pn && e == po) continue;
+            const R B = R(binom2(pm, a) * binom2(pn, b) * binom2(po, e));
+            const R term = B * mu[cm_slot<D>(pm - a, pn - b, po - e)] * c[cm_slot<D>(a + jx, b + jy, e + jz)];
+            acc = FWD ? acc - term : acc + term;
+          }
+      if (FWD)
+        c[k] = acc;
+      else
+        mu[k] = acc;
+    }
+  }
+}
+
+template <int D, class R>
+__device__ __forceinline__ void collide_cu(R *g, const R *s, R ux, R uy, R uz, R src) {
+  constexpr int NQ = D == 2 ? 9 : 27;
+  to_central<D, R>(g, ux, uy, uz);
+  const R k0 = g[0];
+  const R inv = R(1) / k0;
+  g[0] = R(1);
+#pragma unroll
+  for (int k = 1; k < NQ; k++) g[k] *= inv;
+  R c[NQ];
+  c[0] = k0;
+  cumulant_recursion<D, true, R>(g, c);
+#pragma unroll
+  for (int k = 1; k < NQ; k++) {
+    const int m = cm_x<D>(k), n = cm_y<D>(k), o = cm_z<D>(k);
+    const bool var = (m + n + o == 2) && (m == 2 || n == 2 || o == 2);
+    c[k] = c[k] + s[k] * ((var ? R(1) / R(3) : R(0)) - c[k]);
+  }
+  const R psi = k0 + R(0.5) * src;
+  const R c0 = k0 + s[0] * (psi - k0) + (R(1) - R(0.5) * s[0]) * src;
+  cumulant_recursion<D, false, R>(g, c);
+  g[0] = c0;
+#pragma unroll
+  for (int k = 1; k < NQ; k++) g[k] *= c0;
+  from_central<D, R>(g, ux, uy, uz);
+}
+
 // Reverse-mode of collide() for the advection-diffusion lattice, whose
 // collision is affine in (g, src) for a prescribed u:
 //   g* = A g + b src,  A = T^-1 [(1 - S) T + S ceq 1^T],

@@ -50,8 +50,11 @@ void moment_index(int Q, int k, int m[3]) {
 int chimera_index(int Q, const int m[3]) { return Q == 27 ? m[0] * 9 + m[1] * 3 + m[2] : m[0] * 3 + m[1]; }
 
 struct Layout {
-  size_t pop_bytes;  // one copy of one lattice
-  size_t off_pop[2][2];
+  size_t pop_bytes;     // one copy of one lattice
+  size_t region_bytes;  // one copy of every stored lattice
+  size_t off_region[2];
+  size_t off_pop[2][2];  // base of lattice 0 (f) and 1 (h) inside the regions
+  int64_t ps;            // slots per tile, or the FP16 plane stride
   size_t off_cls, off_links, off_walls, off_special, off_groups, off_rho, off_H, off_qx, off_flux, off_part,
       off_res, off_cols, off_side_f, off_side_h, off_side_u;
   size_t total;
@@ -102,6 +105,8 @@ bool validate(const lbm_params *p, std::string *err) {
     return set_err(err, "viscosity nu must be finite and > 0 (got %g)", p->nu);
   if (p->u_mode != 0 && p->u_mode != 1) return set_err(err, "u_mode must be 0 or 1");
   if (p->with_source && p->with_ns) return set_err(err, "a source needs with_ns == 0");
+  if (p->cumulant < 0 || p->cumulant > 3) return set_err(err, "cumulant must be a bit set of 1 (h) and 2 (f)");
+  if ((p->cumulant & 2) && !p->with_ns) return set_err(err, "a cumulant f collision needs with_ns == 1");
   if (p->max_links < 0 || p->max_special < 0) return set_err(err, "max_links/max_special must be >= 0");
   for (int d = 0; d < 3; d++)
     if (!std::isfinite(p->u0[d])) return set_err(err, "u0[%d] is not finite", d);
@@ -142,16 +147,23 @@ Layout layout(const lbm_params *p) {
   const int64_t n = node_count(p);
   const int Q = p->lattice;
   size_t off = 0;
-  // tiles of consecutive nodes with all Q slots each, or Q planes of
-  // plane_nodes() elements (lbm_impl.hpp)
-  L.pop_bytes = align_up((size_t)Q * plane_nodes(n) * storage_size(p->storage));
+  // One region per copy holds every stored lattice (lbm_impl.hpp): tiles of
+  // consecutive nodes with the Q slots of f then of h (FP64/FP32), or Q planes
+  // of plane_nodes() elements per lattice (FP16).
+  const size_t es = storage_size(p->storage);
+  const bool planes = p->storage == LBM_FP16_DEV;
+  const int nlat = p->with_ns ? 2 : 1;
+  L.pop_bytes = align_up((size_t)Q * plane_nodes(n) * es);
+  L.region_bytes = (size_t)nlat * L.pop_bytes;
+  L.ps = planes ? plane_nodes(n) : (int64_t)Q * nlat;
   const int copies = p->stream == LBM_STREAM_AA ? 1 : 2;
-  for (int lat = 0; lat < 2; lat++)
-    for (int c = 0; c < 2; c++) {
-      const bool used = (lat == 1 || p->with_ns) && c < copies;
-      L.off_pop[lat][c] = used ? off : L.off_pop[lat][0];
-      if (used) off += L.pop_bytes;
-    }
+  for (int c = 0; c < 2; c++) {
+    L.off_region[c] = c < copies ? off : L.off_region[0];
+    if (c < copies) off += L.region_bytes;
+    const size_t h_at = !p->with_ns ? 0 : planes ? L.pop_bytes : (size_t)Q * (pop_tile_bytes(Q) / es) * es;
+    L.off_pop[0][c] = L.off_region[c];
+    L.off_pop[1][c] = L.off_region[c] + h_at;
+  }
   L.off_cls = off;
   off += align_up((size_t)n);
   L.off_links = off;
@@ -468,7 +480,7 @@ static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   a.groups = reinterpret_cast<const DevGroup *>(ctx->ws + ctx->L.off_groups);
   a.nspecial = ctx->geom ? ctx->nspecial : 0;
   a.n = ctx->n;
-  a.ps = plane_nodes(ctx->n);
+  a.ps = ctx->L.ps;
   a.nx = ctx->p.nx;
   a.ny = ctx->p.ny;
   a.nz = ctx->p.nz;
@@ -501,7 +513,7 @@ static lbm_status run_pass(lbm_ctx *ctx, int mode, const KArgs &a) {
   if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[ctx->ev_used], ctx->stream), "event record");
   if (mode == MODE_STEP && ctx->geom && ctx->Q == 9) {
     // bulk and boundary nodes in one launch; the boundary time is inside it
-    HIP_TRY(ctx, launch_fused(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->lay(), a, ctx->stream),
+    HIP_TRY(ctx, launch_fused(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->lay(), ctx->p.cumulant, a, ctx->stream),
             "step kernel launch");
     if (timed) {
       HIP_TRY(ctx, hipEventRecord(ctx->ev[ctx->ev_used + 1], ctx->stream), "event record");
@@ -510,11 +522,12 @@ static lbm_status run_pass(lbm_ctx *ctx, int mode, const KArgs &a) {
     }
     return LBM_OK;
   }
-  HIP_TRY(ctx, launch_pass(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->geom, ctx->lay(), mode, a, ctx->stream),
+  HIP_TRY(ctx, launch_pass(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->geom, ctx->lay(), mode, ctx->p.cumulant, a,
+                           ctx->stream),
           "bulk kernel launch");
   if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[ctx->ev_used + 1], ctx->stream), "event record");
   if (ctx->geom)
-    HIP_TRY(ctx, launch_special(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->lay(), mode, a, ctx->stream),
+    HIP_TRY(ctx, launch_special(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->lay(), mode, ctx->p.cumulant, a, ctx->stream),
             "boundary kernel launch");
   if (timed) {
     HIP_TRY(ctx, hipEventRecord(ctx->ev[ctx->ev_used + 2], ctx->stream), "event record");
@@ -754,7 +767,7 @@ lbm_status lbm_init_equilibrium(lbm_ctx *ctx, const double *rho_dev, const doubl
   }
   a.H = H_dev;
   a.n = ctx->n;
-  a.ps = plane_nodes(ctx->n);
+  a.ps = ctx->L.ps;
   a.nx = ctx->p.nx;
   a.ny = ctx->p.ny;
   a.nz = ctx->p.nz;
@@ -902,8 +915,9 @@ lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32
 }
 
 static lbm_status need_adjoint(lbm_ctx *ctx) {
-  if (ctx->p.with_ns || ctx->geom) {
-    set_err(&ctx->err, "the adjoint is built for advection-only contexts without geometry (periodic)");
+  if (ctx->p.with_ns || ctx->geom || (ctx->p.cumulant & 1)) {
+    set_err(&ctx->err, "the adjoint is built for advection-only contexts without geometry (periodic) and with "
+            "the central-moment collision");
     return LBM_EUNSUPPORTED;
   }
   if (ctx->p.u_mode == 1 && !ctx->uvel) {
@@ -956,8 +970,7 @@ lbm_status lbm_adjoint_step(lbm_ctx *ctx, const void *lambda_next_dev, void *lam
 
 size_t lbm_state_bytes(const lbm_ctx *ctx) {
   if (!ctx) return 0;
-  const int lat = ctx->p.with_ns ? 2 : 1;
-  return kAlign + (size_t)lat * ctx->L.pop_bytes;
+  return kAlign + ctx->L.region_bytes;
 }
 
 lbm_status lbm_save_state(lbm_ctx *ctx, void *dst_dev) {
@@ -978,12 +991,8 @@ lbm_status lbm_save_state(lbm_ctx *ctx, void *dst_dev) {
   ctx->hdr.phase = ctx->aa() ? ctx->phase : 0;
   char *d = static_cast<char *>(dst_dev);
   HIP_TRY(ctx, hipMemcpyAsync(d, &ctx->hdr, sizeof(ctx->hdr), hipMemcpyHostToDevice, ctx->stream), "save header");
-  size_t off = kAlign;
-  for (int lat = ctx->p.with_ns ? 0 : 1; lat < 2; lat++) {
-    HIP_TRY(ctx, hipMemcpyAsync(d + off, ctx->pop(lat, ctx->cur), ctx->L.pop_bytes, hipMemcpyDeviceToDevice,
-                                ctx->stream), "save populations");
-    off += ctx->L.pop_bytes;
-  }
+  HIP_TRY(ctx, hipMemcpyAsync(d + kAlign, ctx->ws + ctx->L.off_region[ctx->cur], ctx->L.region_bytes,
+                              hipMemcpyDeviceToDevice, ctx->stream), "save populations");
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "save state");
   return LBM_OK;
 }
@@ -1005,12 +1014,8 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *src_dev) {
     return LBM_EINVAL;
   }
   const char *s = static_cast<const char *>(src_dev);
-  size_t off = kAlign;
-  for (int lat = ctx->p.with_ns ? 0 : 1; lat < 2; lat++) {
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->pop(lat, ctx->cur), s + off, ctx->L.pop_bytes, hipMemcpyDeviceToDevice,
-                                ctx->stream), "load populations");
-    off += ctx->L.pop_bytes;
-  }
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->ws + ctx->L.off_region[ctx->cur], s + kAlign, ctx->L.region_bytes,
+                              hipMemcpyDeviceToDevice, ctx->stream), "load populations");
   ctx->t = h.t;
   ctx->phase = ctx->aa() ? (int)(h.phase & 1) : 0;
   ctx->initialized = true;

@@ -65,50 +65,55 @@ struct StT<ST_FP16_DEV> {
   static constexpr bool DEV = true;
 };
 
-// Population storage of one lattice.  FP64 and FP32 elements: tiles of
-// T = pop_tile_bytes(Q) / sizeof(S) consecutive nodes, each holding its Q slots
-// one after the other, [m / T][tile_pos(slot)][m % T]; a block then reads and
-// writes runs of consecutive bytes per slot and tile, and the slots of a tile
-// share DRAM pages.  Inside a tile the slots of equal (e_z, e_y), which are
-// pulled from one neighbouring row, are adjacent.  FP16 elements: one plane of
-// ps elements per slot, [slot][m], which measured faster for 2-byte elements
-// on MI355X.
+// Population storage.  FP64 and FP32 elements: tiles of
+// T = pop_tile_bytes(Q) / sizeof(S) consecutive nodes; a tile holds the Q
+// slots of every lattice of its nodes one after the other (f then h when both
+// are stored), [m / T][lattice][tile_pos(slot)][m % T], so the buffer of h
+// starts Q T elements after that of f and ps = Q x (number of lattices) slots
+// per tile.  A block then reads and writes runs of consecutive bytes per slot
+// and tile, and all slots of a tile share DRAM pages.  Inside a tile the slots
+// of equal (e_z, e_y), which are pulled from one neighbouring row, are
+// adjacent.  FP16 elements: one plane of ps elements per slot and lattice,
+// [slot][m], which measured faster for 2-byte elements on MI355X.
 template <int Q>
 __device__ __forceinline__ constexpr int tile_pos(int s) {
   return ((Lat<Q>::ez(s) + 1) * 3 + (Lat<Q>::ey(s) + 1)) * 3 + (Lat<Q>::ex(s) + 1) - (Lat<Q>::D == 2 ? 9 : 0);
 }
 
-template <int Q, class S>
+// NL: lattices per tile (1 or 2) when the caller knows it at compile time,
+// else 0 and ps holds the slots per tile.
+template <int Q, class S, int NL>
 __device__ __forceinline__ int64_t pop_index(int slot, int64_t ps, int64_t m) {
   if constexpr (sizeof(S) == 2) {
     return (int64_t)slot * ps + m;
   } else {
     constexpr uint64_t T = pop_tile_bytes(Q) / sizeof(S);
+    const uint64_t spt = NL ? (uint64_t)(Q * NL) : (uint64_t)ps;
     const uint64_t u = (uint64_t)m;
-    return (int64_t)(((u / T) * Q + (uint64_t)tile_pos<Q>(slot)) * T + (u % T));
+    return (int64_t)(((u / T) * spt + (uint64_t)tile_pos<Q>(slot)) * T + (u % T));
   }
 }
 
-// Load / store population i (stored in slot `slot`) of node m; ps is the plane
-// stride of the FP16 layout.  The deviation storages keep g_i - w_i g_ref;
+// Load / store population i (stored in slot `slot`) of node m; ps is the
+// slots per tile (FP64/FP32) or the plane stride (FP16) of the layout.  The deviation storages keep g_i - w_i g_ref;
 // w_i = w_opp(i), so a swapped slot needs no other weight.
-template <int Q, int ST>
+template <int Q, int ST, int NL = 0>
 __device__ __forceinline__ typename StT<ST>::R ldp(const void *base, int slot, int64_t ps, int64_t m,
                                                    typename StT<ST>::R ref) {
   using T = StT<ST>;
   using R = typename T::R;
-  const typename T::S *p = static_cast<const typename T::S *>(base) + pop_index<Q, typename T::S>(slot, ps, m);
+  const typename T::S *p = static_cast<const typename T::S *>(base) + pop_index<Q, typename T::S, NL>(slot, ps, m);
   R v = StoreT<typename T::S>::ld(p);
   if constexpr (T::DEV) v += weight<Q, R>(slot) * ref;
   return v;
 }
 
-template <int Q, int ST>
+template <int Q, int ST, int NL = 0>
 __device__ __forceinline__ void stp(void *base, int slot, int64_t ps, int64_t m, typename StT<ST>::R v,
                                     typename StT<ST>::R ref) {
   using T = StT<ST>;
   if constexpr (T::DEV) v -= weight<Q, typename T::R>(slot) * ref;
-  typename T::S *p = static_cast<typename T::S *>(base) + pop_index<Q, typename T::S>(slot, ps, m);
+  typename T::S *p = static_cast<typename T::S *>(base) + pop_index<Q, typename T::S, NL>(slot, ps, m);
   StoreT<typename T::S>::st(p, v);
 }
 
@@ -252,7 +257,9 @@ __device__ __forceinline__ void post_addr(const KArgs &a, Node c, int64_t m, int
 // collide and store (f, h then hold the stored post-collision values), or
 // write them / their moments out.
 // ---------------------------------------------------------------------------
-template <int Q, int ST, bool NS, int MODE, int LAY>
+// CU selects the collision of each lattice: bit 0 h, bit 1 f use the cumulant
+// collision (Eqs. hydro_cu_collision, H_cu_collision), else central moments.
+template <int Q, int ST, bool NS, int MODE, int LAY, int CU = 0>
 __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, typename StT<ST>::R *f,
                                             typename StT<ST>::R *h) {
   using R = typename StT<ST>::R;
@@ -268,26 +275,32 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
     if constexpr (NS) {
 #pragma unroll
       for (int i = 0; i < Q; i++) g[Lat<Q>::slot(i)] = f[i];
-      collide<D, R>(g, rates<R>(a, true), ux, uy, uz, R(0));
+      if constexpr (CU & 2)
+        collide_cu<D, R>(g, rates<R>(a, true), ux, uy, uz, R(0));
+      else
+        collide<D, R>(g, rates<R>(a, true), ux, uy, uz, R(0));
 #pragma unroll
       for (int i = 0; i < Q; i++) {
         int sl;
         int64_t nd;
         store_addr<Q, LAY>(a, c, m, i, sl, nd);
         f[i] = g[Lat<Q>::slot(i)];
-        stp<Q, ST>(a.fdst, sl, a.ps, nd, f[i], R(a.fref));
+        stp<Q, ST, NS ? 2 : 1>(a.fdst, sl, a.ps, nd, f[i], R(a.fref));
       }
     }
 #pragma unroll
     for (int i = 0; i < Q; i++) g[Lat<Q>::slot(i)] = h[i];
-    collide<D, R>(g, rates<R>(a, false), ux, uy, uz, src);
+    if constexpr (CU & 1)
+      collide_cu<D, R>(g, rates<R>(a, false), ux, uy, uz, src);
+    else
+      collide<D, R>(g, rates<R>(a, false), ux, uy, uz, src);
 #pragma unroll
     for (int i = 0; i < Q; i++) {
       int sl;
       int64_t nd;
       store_addr<Q, LAY>(a, c, m, i, sl, nd);
       h[i] = g[Lat<Q>::slot(i)];
-      stp<Q, ST>(a.hdst, sl, a.ps, nd, h[i], R(a.href));
+      stp<Q, ST, NS ? 2 : 1>(a.hdst, sl, a.ps, nd, h[i], R(a.href));
     }
   } else if constexpr (MODE == MODE_PRE) {
 #pragma unroll
@@ -401,7 +414,7 @@ __device__ __forceinline__ void eq_node(const KArgs &a, int64_t m, int g, typena
 // outlet node (zero gradient along x) takes the e_x < 0 populations of its
 // upstream node x - 1, which the previous lane of the same wavefront has just
 // pulled (that node has no cut links, so these are its final values).
-template <int Q, int ST, bool NS, bool GEOM, int MODE, int LAY>
+template <int Q, int ST, bool NS, bool GEOM, int MODE, int LAY, int CU = 0>
 __device__ __forceinline__ void bulk_node(const KArgs &a, int64_t m) {
   using R = typename StT<ST>::R;
   if (m >= a.n) return;
@@ -414,8 +427,8 @@ __device__ __forceinline__ void bulk_node(const KArgs &a, int64_t m) {
     int sl;
     int64_t nd;
     pull_addr<Q, LAY>(a, c, m, i, sl, nd);
-    if constexpr (NS) f[i] = ldp<Q, ST>(a.fsrc, sl, a.ps, nd, R(a.fref));
-    h[i] = ldp<Q, ST>(a.hsrc, sl, a.ps, nd, R(a.href));
+    if constexpr (NS) f[i] = ldp<Q, ST, NS ? 2 : 1>(a.fsrc, sl, a.ps, nd, R(a.fref));
+    h[i] = ldp<Q, ST, NS ? 2 : 1>(a.hsrc, sl, a.ps, nd, R(a.href));
   }
   if constexpr (GEOM) {
     if (__ballot(cl == CLS_OUTLET)) {
@@ -437,13 +450,13 @@ __device__ __forceinline__ void bulk_node(const KArgs &a, int64_t m) {
     if (cl == CLS_SPECIAL) return;
     if (cl >= CLS_EQ) eq_node<Q, ST, NS>(a, m, cl - CLS_EQ, f, h);
   }
-  finish_node<Q, ST, NS, MODE, LAY>(a, c, m, f, h);
+  finish_node<Q, ST, NS, MODE, LAY, CU>(a, c, m, f, h);
 }
 
-template <int Q, int ST, bool NS, bool GEOM, int MODE, int LAY>
+template <int Q, int ST, bool NS, bool GEOM, int MODE, int LAY, int CU = 0>
 __global__ void __launch_bounds__(256) k_bulk(const KArgs a) {
   const int64_t tile = tile_of(a, blockIdx.x, gridDim.x);
-  bulk_node<Q, ST, NS, GEOM, MODE, LAY>(a, tile * 256 + threadIdx.x);
+  bulk_node<Q, ST, NS, GEOM, MODE, LAY, CU>(a, tile * 256 + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -470,8 +483,8 @@ __device__ __forceinline__ void pull_links(const KArgs &a, int64_t m, int32_t lb
     int sl;
     int64_t nd;
     pull_addr<Q, LAY>(a, c, m, i, sl, nd);
-    if constexpr (NS) f[i] = ldp<Q, ST>(a.fsrc, sl, a.ps, nd, fref);
-    h[i] = ldp<Q, ST>(a.hsrc, sl, a.ps, nd, href);
+    if constexpr (NS) f[i] = ldp<Q, ST, NS ? 2 : 1>(a.fsrc, sl, a.ps, nd, fref);
+    h[i] = ldp<Q, ST, NS ? 2 : 1>(a.hsrc, sl, a.ps, nd, href);
   }
   if (mask == 0) return;
   // g*_i(x_b) and g*_opp(i)(x_b) of step t-1 per link direction i: in AB the
@@ -484,8 +497,8 @@ __device__ __forceinline__ void pull_links(const KArgs &a, int64_t m, int32_t lb
   if constexpr (AB) {
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-      if constexpr (NS) fbi[i] = ldp<Q, ST>(a.fsrc, i, a.ps, m, fref);
-      hbi[i] = ldp<Q, ST>(a.hsrc, i, a.ps, m, href);
+      if constexpr (NS) fbi[i] = ldp<Q, ST, NS ? 2 : 1>(a.fsrc, i, a.ps, m, fref);
+      hbi[i] = ldp<Q, ST, NS ? 2 : 1>(a.hsrc, i, a.ps, m, href);
     }
   }
 #pragma unroll
@@ -498,10 +511,10 @@ __device__ __forceinline__ void pull_links(const KArgs &a, int64_t m, int32_t lb
       int64_t nd;
       post_addr<Q, LAY>(a, c, m, i, sl, nd);
       if constexpr (NS) {
-        fbi[i] = ldp<Q, ST>(a.fsrc, sl, a.ps, nd, fref);
+        fbi[i] = ldp<Q, ST, NS ? 2 : 1>(a.fsrc, sl, a.ps, nd, fref);
         fbo[i] = static_cast<const R *>(a.side_f)[l];
       }
-      hbi[i] = ldp<Q, ST>(a.hsrc, sl, a.ps, nd, href);
+      hbi[i] = ldp<Q, ST, NS ? 2 : 1>(a.hsrc, sl, a.ps, nd, href);
       hbo[i] = static_cast<const R *>(a.side_h)[l];
     }
   }
@@ -577,7 +590,7 @@ __device__ __forceinline__ void save_side(const KArgs &a, int32_t lb, uint32_t m
   }
 }
 
-template <int Q, int ST, bool NS, int MODE, int LAY>
+template <int Q, int ST, bool NS, int MODE, int LAY, int CU = 0>
 __device__ __forceinline__ void special_node(const KArgs &a, int64_t t) {
   using R = typename StT<ST>::R;
   constexpr bool AA = LAY != LAY_AB;
@@ -605,39 +618,39 @@ __device__ __forceinline__ void special_node(const KArgs &a, int64_t t) {
         }
       }
       if constexpr (AA) {
-        finish_node<Q, ST, NS, MODE, LAY>(a, coords(a, up), up, fu, hu);
+        finish_node<Q, ST, NS, MODE, LAY, CU>(a, coords(a, up), up, fu, hu);
         if constexpr (MODE == MODE_STEP) save_side<Q, ST, NS>(a, sp.ub, sp.umask, 2 * t + 1, fu, hu);
       }
     }
   }
-  finish_node<Q, ST, NS, MODE, LAY>(a, c, m, f, h);
+  finish_node<Q, ST, NS, MODE, LAY, CU>(a, c, m, f, h);
   if constexpr (AA && MODE == MODE_STEP) save_side<Q, ST, NS>(a, sp.lb, sp.mask, 2 * t, f, h);
 }
 
-template <int Q, int ST, bool NS, int MODE, int LAY>
+template <int Q, int ST, bool NS, int MODE, int LAY, int CU = 0>
 __global__ void __launch_bounds__(64) k_special(const KArgs a) {
-  special_node<Q, ST, NS, MODE, LAY>(a, (int64_t)blockIdx.x * 64 + threadIdx.x);
+  special_node<Q, ST, NS, MODE, LAY, CU>(a, (int64_t)blockIdx.x * 64 + threadIdx.x);
 }
 
 // One launch per step with geometry (D2Q9): the first `sblocks` blocks (a
 // multiple of 8, so the XCD of a bulk block is unchanged) take the boundary
 // nodes, whose long chains of dependent loads then overlap the bulk stream
 // instead of running after it.
-template <int Q, int ST, bool NS, int LAY>
+template <int Q, int ST, bool NS, int LAY, int CU>
 __device__ __forceinline__ void fused_body(const KArgs &a, int sblocks) {
   if ((int)blockIdx.x < sblocks) {
-    special_node<Q, ST, NS, MODE_STEP, LAY>(a, (int64_t)blockIdx.x * 256 + threadIdx.x);
+    special_node<Q, ST, NS, MODE_STEP, LAY, CU>(a, (int64_t)blockIdx.x * 256 + threadIdx.x);
     return;
   }
   const int64_t tile = tile_of(a, blockIdx.x - sblocks, gridDim.x - sblocks);
-  bulk_node<Q, ST, NS, true, MODE_STEP, LAY>(a, tile * 256 + threadIdx.x);
+  bulk_node<Q, ST, NS, true, MODE_STEP, LAY, CU>(a, tile * 256 + threadIdx.x);
 }
 
 // (The scalar state of the boundary path limits this launch to 7 waves per
 // SIMD where the bulk kernel runs 8; forcing 8 measured slower on MI355X.)
-template <int Q, int ST, bool NS, int LAY>
+template <int Q, int ST, bool NS, int LAY, int CU>
 __global__ void __launch_bounds__(256) k_fused(const KArgs a, int sblocks) {
-  fused_body<Q, ST, NS, LAY>(a, sblocks);
+  fused_body<Q, ST, NS, LAY, CU>(a, sblocks);
 }
 
 // AA side buffers from the stored state (after init, set or load).
@@ -657,9 +670,9 @@ __global__ void __launch_bounds__(64) k_side(const KArgs a) {
       int sl;
       int64_t nd;
       post_addr<Q, LAY>(a, c, m, i, sl, nd);
-      if constexpr (NS) f[i] = ldp<Q, ST>(a.fsrc, sl, a.ps, nd, R(a.fref));
+      if constexpr (NS) f[i] = ldp<Q, ST, NS ? 2 : 1>(a.fsrc, sl, a.ps, nd, R(a.fref));
       else f[i] = R(0);
-      h[i] = ldp<Q, ST>(a.hsrc, sl, a.ps, nd, R(a.href));
+      h[i] = ldp<Q, ST, NS ? 2 : 1>(a.hsrc, sl, a.ps, nd, R(a.href));
     }
     save_side<Q, ST, NS>(a, k == 0 ? sp.lb : sp.ub, k == 0 ? sp.mask : sp.umask, 2 * t + k, f, h);
   }
@@ -703,9 +716,9 @@ __global__ void __launch_bounds__(256) k_init(const InitArgs a) {
     const int slot = LAY == LAY_AB ? i : Lat<Q>::opp(i);
     if constexpr (NS) {
       const double rho = a.rho ? a.rho[s] : 1.0;
-      stp<Q, ST>(a.fdst, slot, a.ps, m, R(geq_dir<Q, double>(i, rho, ux, uy, uz)), R(a.fref));
+      stp<Q, ST, NS ? 2 : 1>(a.fdst, slot, a.ps, m, R(geq_dir<Q, double>(i, rho, ux, uy, uz)), R(a.fref));
     }
-    stp<Q, ST>(a.hdst, slot, a.ps, m, R(geq_dir<Q, double>(i, a.H[s], ux, uy, uz)), R(a.href));
+    stp<Q, ST, NS ? 2 : 1>(a.hdst, slot, a.ps, m, R(geq_dir<Q, double>(i, a.H[s], ux, uy, uz)), R(a.href));
   }
 }
 
@@ -793,11 +806,45 @@ static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b -
       return hipErrorInvalidValue;      \
   }
 
+// cu (bit 0 h, bit 1 f: cumulant collision) as a compile-time CU for CALL;
+// f bits need the hydrodynamic lattice.
+#define LBM_DISPATCH_CU(NS_VAL, CU_VAL, CALL) \
+  switch (CU_VAL) {                           \
+    case 0: {                                 \
+      constexpr int CU = 0;                   \
+      CALL;                                   \
+      break;                                  \
+    }                                         \
+    case 1: {                                 \
+      constexpr int CU = 1;                   \
+      CALL;                                   \
+      break;                                  \
+    }                                         \
+    case 2:                                   \
+      if constexpr (NS_VAL) {                 \
+        constexpr int CU = 2;                 \
+        CALL;                                 \
+        break;                                \
+      } else {                                \
+        return hipErrorInvalidValue;          \
+      }                                       \
+    case 3:                                   \
+      if constexpr (NS_VAL) {                 \
+        constexpr int CU = 3;                 \
+        CALL;                                 \
+        break;                                \
+      } else {                                \
+        return hipErrorInvalidValue;          \
+      }                                       \
+    default:                                  \
+      return hipErrorInvalidValue;            \
+  }
+
 template <int Q, int ST, bool NS, bool GEOM, int LAY>
-static hipError_t pass_t(int mode, const KArgs &a, hipStream_t s) {
+static hipError_t pass_t(int mode, int cu, const KArgs &a, hipStream_t s) {
   const unsigned g = blocks_for(a.n, 256);
   if (mode == MODE_STEP)
-    k_bulk<Q, ST, NS, GEOM, MODE_STEP, LAY><<<g, 256, 0, s>>>(a);
+    LBM_DISPATCH_CU(NS, cu, (k_bulk<Q, ST, NS, GEOM, MODE_STEP, LAY, CU><<<g, 256, 0, s>>>(a)))
   else if (mode == MODE_PRE)
     k_bulk<Q, ST, NS, GEOM, MODE_PRE, LAY><<<g, 256, 0, s>>>(a);
   else
@@ -806,11 +853,11 @@ static hipError_t pass_t(int mode, const KArgs &a, hipStream_t s) {
 }
 
 template <int Q, int ST, bool NS, int LAY>
-static hipError_t special_t(int mode, const KArgs &a, hipStream_t s) {
+static hipError_t special_t(int mode, int cu, const KArgs &a, hipStream_t s) {
   if (a.nspecial == 0) return hipSuccess;
   const unsigned g = blocks_for(a.nspecial, 64);
   if (mode == MODE_STEP)
-    k_special<Q, ST, NS, MODE_STEP, LAY><<<g, 64, 0, s>>>(a);
+    LBM_DISPATCH_CU(NS, cu, (k_special<Q, ST, NS, MODE_STEP, LAY, CU><<<g, 64, 0, s>>>(a)))
   else if (mode == MODE_PRE)
     k_special<Q, ST, NS, MODE_PRE, LAY><<<g, 64, 0, s>>>(a);
   else
@@ -819,9 +866,9 @@ static hipError_t special_t(int mode, const KArgs &a, hipStream_t s) {
 }
 
 template <int Q, int ST, bool NS, int LAY>
-static hipError_t fused_t(const KArgs &a, hipStream_t s) {
+static hipError_t fused_t(int cu, const KArgs &a, hipStream_t s) {
   const int sblocks = (int)((blocks_for(a.nspecial, 256) + 7) / 8 * 8);
-  k_fused<Q, ST, NS, LAY><<<blocks_for(a.n, 256) + sblocks, 256, 0, s>>>(a, sblocks);
+  LBM_DISPATCH_CU(NS, cu, (k_fused<Q, ST, NS, LAY, CU><<<blocks_for(a.n, 256) + sblocks, 256, 0, s>>>(a, sblocks)))
   return hipGetLastError();
 }
 
@@ -858,31 +905,31 @@ static hipError_t adjoint_t(const KArgs &a, const void *ln, void *lp, void *dq, 
 // plain names in one translation unit per pair (compiled in parallel).
 template <int Q, int ST>
 struct Launch {
-  static hipError_t pass(bool ns, bool geom, int lay, int mode, const KArgs &a, hipStream_t s) {
+  static hipError_t pass(bool ns, bool geom, int lay, int mode, int cu, const KArgs &a, hipStream_t s) {
     if (ns) {
-      if (geom) return pass_lay<true, true>(lay, mode, a, s);
-      return pass_lay<true, false>(lay, mode, a, s);
+      if (geom) return pass_lay<true, true>(lay, mode, cu, a, s);
+      return pass_lay<true, false>(lay, mode, cu, a, s);
     }
-    if (geom) return pass_lay<false, true>(lay, mode, a, s);
-    return pass_lay<false, false>(lay, mode, a, s);
+    if (geom) return pass_lay<false, true>(lay, mode, cu, a, s);
+    return pass_lay<false, false>(lay, mode, cu, a, s);
   }
   template <bool NS, bool GEOM>
-  static hipError_t pass_lay(int lay, int mode, const KArgs &a, hipStream_t s) {
-    LBM_DISPATCH_LAY(lay, (pass_t<Q, ST, NS, GEOM, LAY>(mode, a, s)))
+  static hipError_t pass_lay(int lay, int mode, int cu, const KArgs &a, hipStream_t s) {
+    LBM_DISPATCH_LAY(lay, (pass_t<Q, ST, NS, GEOM, LAY>(mode, cu, a, s)))
   }
-  static hipError_t special(bool ns, int lay, int mode, const KArgs &a, hipStream_t s) {
-    return ns ? special_lay<true>(lay, mode, a, s) : special_lay<false>(lay, mode, a, s);
-  }
-  template <bool NS>
-  static hipError_t special_lay(int lay, int mode, const KArgs &a, hipStream_t s) {
-    LBM_DISPATCH_LAY(lay, (special_t<Q, ST, NS, LAY>(mode, a, s)))
-  }
-  static hipError_t fused(bool ns, int lay, const KArgs &a, hipStream_t s) {
-    return ns ? fused_lay<true>(lay, a, s) : fused_lay<false>(lay, a, s);
+  static hipError_t special(bool ns, int lay, int mode, int cu, const KArgs &a, hipStream_t s) {
+    return ns ? special_lay<true>(lay, mode, cu, a, s) : special_lay<false>(lay, mode, cu, a, s);
   }
   template <bool NS>
-  static hipError_t fused_lay(int lay, const KArgs &a, hipStream_t s) {
-    LBM_DISPATCH_LAY(lay, (fused_t<Q, ST, NS, LAY>(a, s)))
+  static hipError_t special_lay(int lay, int mode, int cu, const KArgs &a, hipStream_t s) {
+    LBM_DISPATCH_LAY(lay, (special_t<Q, ST, NS, LAY>(mode, cu, a, s)))
+  }
+  static hipError_t fused(bool ns, int lay, int cu, const KArgs &a, hipStream_t s) {
+    return ns ? fused_lay<true>(lay, cu, a, s) : fused_lay<false>(lay, cu, a, s);
+  }
+  template <bool NS>
+  static hipError_t fused_lay(int lay, int cu, const KArgs &a, hipStream_t s) {
+    LBM_DISPATCH_LAY(lay, (fused_t<Q, ST, NS, LAY>(cu, a, s)))
   }
   static hipError_t side(bool ns, int lay, const KArgs &a, hipStream_t s) {
     return ns ? side_lay<true>(lay, a, s) : side_lay<false>(lay, a, s);
@@ -912,14 +959,14 @@ struct Launch {
 };
 
 #define LBM_INSTANTIATE(Q, ST, NAME)                                                                          \
-  hipError_t NAME##_pass(bool ns, bool geom, int lay, int mode, const KArgs &a, hipStream_t s) {              \
-    return Launch<Q, ST>::pass(ns, geom, lay, mode, a, s);                                                    \
+  hipError_t NAME##_pass(bool ns, bool geom, int lay, int mode, int cu, const KArgs &a, hipStream_t s) {      \
+    return Launch<Q, ST>::pass(ns, geom, lay, mode, cu, a, s);                                                \
   }                                                                                                           \
-  hipError_t NAME##_special(bool ns, int lay, int mode, const KArgs &a, hipStream_t s) {                      \
-    return Launch<Q, ST>::special(ns, lay, mode, a, s);                                                       \
+  hipError_t NAME##_special(bool ns, int lay, int mode, int cu, const KArgs &a, hipStream_t s) {              \
+    return Launch<Q, ST>::special(ns, lay, mode, cu, a, s);                                                   \
   }                                                                                                           \
-  hipError_t NAME##_fused(bool ns, int lay, const KArgs &a, hipStream_t s) {                                  \
-    return Launch<Q, ST>::fused(ns, lay, a, s);                                                               \
+  hipError_t NAME##_fused(bool ns, int lay, int cu, const KArgs &a, hipStream_t s) {                          \
+    return Launch<Q, ST>::fused(ns, lay, cu, a, s);                                                           \
   }                                                                                                           \
   hipError_t NAME##_side(bool ns, int lay, const KArgs &a, hipStream_t s) {                                   \
     return Launch<Q, ST>::side(ns, lay, a, s);                                                                \

@@ -6,9 +6,9 @@
 namespace lbm {
 
 #define LBM_DECLARE(NAME)                                                                             \
-  hipError_t NAME##_pass(bool, bool, int, int, const KArgs &, hipStream_t);                           \
-  hipError_t NAME##_special(bool, int, int, const KArgs &, hipStream_t);                              \
-  hipError_t NAME##_fused(bool, int, const KArgs &, hipStream_t);                                     \
+  hipError_t NAME##_pass(bool, bool, int, int, int, const KArgs &, hipStream_t);                      \
+  hipError_t NAME##_special(bool, int, int, int, const KArgs &, hipStream_t);                         \
+  hipError_t NAME##_fused(bool, int, int, const KArgs &, hipStream_t);                                \
   hipError_t NAME##_side(bool, int, const KArgs &, hipStream_t);                                      \
   hipError_t NAME##_init(bool, int, const InitArgs &, hipStream_t);                                   \
   hipError_t NAME##_convert(int, bool, const KArgs &, const void *, void *, double, hipStream_t);      \
@@ -44,14 +44,15 @@ LBM_DECLARE(q27_fp16dev)
     return hipErrorInvalidValue;                                               \
   } while (0)
 
-hipError_t launch_pass(int Q, int storage, bool ns, bool geom, int lay, int mode, const KArgs &a, hipStream_t s) {
-  LBM_SELECT(Q, storage, pass, ns, geom, lay, mode, a, s);
+hipError_t launch_pass(int Q, int storage, bool ns, bool geom, int lay, int mode, int cu, const KArgs &a,
+                       hipStream_t s) {
+  LBM_SELECT(Q, storage, pass, ns, geom, lay, mode, cu, a, s);
 }
-hipError_t launch_special(int Q, int storage, bool ns, int lay, int mode, const KArgs &a, hipStream_t s) {
-  LBM_SELECT(Q, storage, special, ns, lay, mode, a, s);
+hipError_t launch_special(int Q, int storage, bool ns, int lay, int mode, int cu, const KArgs &a, hipStream_t s) {
+  LBM_SELECT(Q, storage, special, ns, lay, mode, cu, a, s);
 }
-hipError_t launch_fused(int Q, int storage, bool ns, int lay, const KArgs &a, hipStream_t s) {
-  LBM_SELECT(Q, storage, fused, ns, lay, a, s);
+hipError_t launch_fused(int Q, int storage, bool ns, int lay, int cu, const KArgs &a, hipStream_t s) {
+  LBM_SELECT(Q, storage, fused, ns, lay, cu, a, s);
 }
 hipError_t launch_side(int Q, int storage, bool ns, int lay, const KArgs &a, hipStream_t s) {
   LBM_SELECT(Q, storage, side, ns, lay, a, s);

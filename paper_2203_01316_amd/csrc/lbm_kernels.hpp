@@ -97,7 +97,7 @@ struct KArgs {
   const DevGroup *groups;
   int64_t nspecial;
   int64_t n;
-  int64_t ps;              // plane stride of the FP16 population layout
+  int64_t ps;              // population layout: slots per tile, or the FP16 plane stride
   int32_t nx, ny, nz;
   int32_t with_uvel;       // advection velocity from the field (else u0)
   int32_t tilemap;         // block -> tile order: 0 one slab per XCD, 1 rows per XCD,
@@ -125,7 +125,7 @@ struct InitArgs {
   const void *uvel;   // fallback field, arithmetic type, or null
   const double *H;    // [n]
   int64_t n;
-  int64_t ps;         // plane stride of the FP16 population layout
+  int64_t ps;         // population layout: slots per tile, or the FP16 plane stride
   int32_t nx, ny, nz;
   double u0[3];
   double fref, href;
@@ -134,12 +134,14 @@ struct InitArgs {
 // storage codes (lbm_storage)
 enum : int { ST_FP64 = 0, ST_FP32 = 1, ST_FP32_DEV = 2, ST_FP16_DEV = 3 };
 
-// Launchers; return hipSuccess or the launch error.  lay: LAY_*.
-hipError_t launch_pass(int Q, int storage, bool ns, bool geom, int lay, int mode, const KArgs &a,
+// Launchers; return hipSuccess or the launch error.  lay: LAY_*.  cu: the
+// collision of each lattice in MODE_STEP (bit 0 h, bit 1 f: cumulants, else
+// central moments).
+hipError_t launch_pass(int Q, int storage, bool ns, bool geom, int lay, int mode, int cu, const KArgs &a,
                        hipStream_t s);
-hipError_t launch_special(int Q, int storage, bool ns, int lay, int mode, const KArgs &a, hipStream_t s);
+hipError_t launch_special(int Q, int storage, bool ns, int lay, int mode, int cu, const KArgs &a, hipStream_t s);
 // D2Q9 step with geometry: boundary and bulk nodes in one launch.
-hipError_t launch_fused(int Q, int storage, bool ns, int lay, const KArgs &a, hipStream_t s);
+hipError_t launch_fused(int Q, int storage, bool ns, int lay, int cu, const KArgs &a, hipStream_t s);
 // AA side buffers from the stored state.
 hipError_t launch_side(int Q, int storage, bool ns, int lay, const KArgs &a, hipStream_t s);
 hipError_t launch_init(int Q, int storage, bool ns, int lay, const InitArgs &a, hipStream_t s);

@@ -40,7 +40,7 @@ class Params(C.Structure):
                 ("with_ns", C.c_int32), ("storage", C.c_int32), ("stream", C.c_int32),
                 ("relax_f", C.c_int32), ("relax_h", C.c_int32), ("u_mode", C.c_int32),
                 ("with_source", C.c_int32), ("max_links", C.c_int32), ("max_special", C.c_int32),
-                ("reserved", C.c_int32), ("nu", C.c_double), ("k", C.c_double),
+                ("cumulant", C.c_int32), ("nu", C.c_double), ("k", C.c_double),
                 ("rho_ref", C.c_double), ("H_ref", C.c_double), ("u0", C.c_double * 3),
                 ("s_custom_f", C.c_double * 27), ("s_custom_h", C.c_double * 27)]
 
@@ -116,7 +116,9 @@ def version() -> str:
 def make_params(lattice=D2Q9, nx=64, ny=64, nz=1, *, with_ns=False, storage="fp64", stream=STREAM_AB,
                 relax_f="ns", relax_h="trt", nu=0.0, k=0.01, u0=(0.0, 0.0, 0.0), u_mode=0,
                 with_source=False, max_links=0, max_special=0, rho_ref=0.0, H_ref=0.0,
-                s_custom_f=None, s_custom_h=None) -> Params:
+                s_custom_f=None, s_custom_h=None, cumulant_f=False, cumulant_h=False) -> Params:
+    """Library parameters.  cumulant_f / cumulant_h select the cumulant
+    collision for that lattice (relax_h="1st" is the paper's Cumulants-1st)."""
     p = Params()
     p.lattice, p.nx, p.ny, p.nz = int(lattice), int(nx), int(ny), int(nz)
     p.with_ns = int(bool(with_ns))
@@ -126,6 +128,7 @@ def make_params(lattice=D2Q9, nx=64, ny=64, nz=1, *, with_ns=False, storage="fp6
     p.relax_h = _RELAX[relax_h] if isinstance(relax_h, str) else int(relax_h)
     p.u_mode = int(u_mode)
     p.with_source = int(bool(with_source))
+    p.cumulant = (1 if cumulant_h else 0) | (2 if cumulant_f else 0)
     p.max_links, p.max_special = int(max_links), int(max_special)
     p.nu, p.k = float(nu), float(k)
     p.rho_ref, p.H_ref = float(rho_ref), float(H_ref)

@@ -25,7 +25,8 @@ def fluid_only(arr, flags):
 
 
 def pair(L, O, *, Q, dims, storage="fp64", with_ns=False, relax_h="trt", nu=0.0, k=0.01, u0=(0, 0, 0),
-         uvel=None, src=None, flags=None, q=None, groups=(), H0=None, u_init=None, rho0=None, oracle_init=True):
+         uvel=None, src=None, flags=None, q=None, groups=(), H0=None, u_init=None, rho0=None, oracle_init=True,
+         cu_f=False, cu_h=False, stream=0, rho_ref=0.0, H_ref=0.0):
     """GPU context and oracle simulation over identical inputs, both at t = 0."""
     nx, ny, nz = dims
     n = nx * ny * nz
@@ -34,7 +35,8 @@ def pair(L, O, *, Q, dims, storage="fp64", with_ns=False, relax_h="trt", nu=0.0,
     uv = None if uvel is None else cast(np.asarray(uvel).reshape(3, n))
     sr = None if src is None else cast(np.asarray(src).reshape(n))
     kw = dict(with_ns=with_ns, storage=storage, relax_h=relax_h, relax_f="ns", nu=nu, k=k, u0=u0,
-              u_mode=1 if uv is not None and not with_ns else 0, with_source=src is not None)
+              u_mode=1 if uv is not None and not with_ns else 0, with_source=src is not None,
+              cumulant_f=cu_f, cumulant_h=cu_h, stream=stream, rho_ref=rho_ref, H_ref=H_ref)
     g = L.LBM(Q, nx, ny, nz, flags=flags, q=q, groups=groups, **kw)
     if uv is not None:
         g.set_velocity(uv)
@@ -42,7 +44,7 @@ def pair(L, O, *, Q, dims, storage="fp64", with_ns=False, relax_h="trt", nu=0.0,
         g.set_source(sr)
     sf, sh = L.relaxation_rates(g.params)
     o = O.Sim(Q, nx, ny, nz, with_ns=with_ns, s_f=sf, s_h=sh, u0=u0, uvel=uv, src=sr, flags=flags, qlink=q,
-              groups=list(groups))
+              groups=list(groups), cu_f=cu_f, cu_h=cu_h)
     H0 = np.ones(n) if H0 is None else np.asarray(H0, float).reshape(n)
     g.init(H0, u=u_init, rho=rho0)
     if oracle_init:

@@ -50,6 +50,7 @@ def test_version_and_workspace(L):
     (dict(lattice=15), "lattice"),
     (dict(stream=7), "stream mode"),
     (dict(nx=0), "nx, ny, nz"),
+    (dict(cumulant_f=True), "cumulant f collision needs with_ns"),
     (dict(ny=-3), "nx, ny, nz"),
     (dict(with_source=True, with_ns=True, nu=0.1), "source"),
 ])

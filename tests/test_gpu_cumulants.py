@@ -1,0 +1,149 @@
+"""GPU parity of the cumulant collision (Sec. 2.1.1, Eqs. hydro_cu_collision
+and H_cu_collision, source of App. D) against the FP64 oracle: the
+advection-diffusion lattice with the Cumulants-1st kernel, the hydrodynamic
+lattice with the cumulant kernel (second-order cumulants at s_nu), and the
+paper's combination of a cumulant f with a central-moment h."""
+import numpy as np
+import pytest
+
+from paper_2203_01316_amd import workloads as W
+
+from gpu_common import f32, fluid_only, gpu_post, gpu_pre, pair, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2203_01316_amd import lbm
+    return lbm
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_cumulants_first_gaussian_hill(L, oracle, storage, tol):
+    H0 = W.gaussian_hill(64, 8.0, 0.5, None, (0.05, 0.02), 0.01, 0.0)
+    g, o = pair(L, oracle, Q=9, dims=(64, 64, 1), storage=storage, relax_h="1st", k=0.01, u0=(0.05, 0.02, 0),
+                H0=H0, cu_h=True)
+    g.step(500)
+    o.step(500)
+    assert rel_l2(gpu_pre(g), o.pre()[1]) < tol
+    if storage == "fp64":
+        _, _, Hg = g.macroscopic()
+        ana = W.gaussian_hill(64, 8.0, 0.5, None, (0.05, 0.02), 0.01, 500.0)
+        assert rel_l2(Hg.cpu().numpy(), ana) < 6e-4
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_cumulants_first_with_source_and_field(L, oracle, storage, tol):
+    rng = np.random.default_rng(41)
+    n = 37 * 23
+    u = np.zeros((3, n))
+    u[:2] = rng.uniform(-0.04, 0.04, (2, n))
+    src = 0.01 * rng.standard_normal(n)
+    g, o = pair(L, oracle, Q=9, dims=(37, 23, 1), storage=storage, relax_h="1st", k=0.02, uvel=u, src=src,
+                H0=1 + 0.1 * rng.uniform(size=n), cu_h=True)
+    g.step(60)
+    o.step(60)
+    assert rel_l2(gpu_pre(g), o.pre()[1]) < tol
+
+
+@pytest.mark.parametrize("cu_h", [False, True])
+@pytest.mark.parametrize("storage,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_cumulant_f_coupled_cylinder(L, oracle, storage, tol, cu_h):
+    """Heated cylinder (IBB/IABB, EQ inlet, outlet): cumulant f with a
+    central-moment (CM-TRT) or Cumulants-1st h."""
+    flags, q, groups, u, rho0, H0 = W.heated_cylinder(192, 96, 9.5, u_in=0.04, amp=1e-3, seed=0)
+    g, o = pair(L, oracle, Q=9, dims=(192, 96, 1), storage=storage, with_ns=True, nu=0.04, k=0.06, uvel=u,
+                flags=flags, q=q, groups=groups, H0=H0, u_init=f32(u) if storage != "fp64" else u, rho0=rho0,
+                relax_h="1st" if cu_h else "trt", cu_f=True, cu_h=cu_h)
+    g.step(300)
+    o.step(300)
+    fo, ho = o.pre()
+    assert rel_l2(gpu_pre(g, "f"), fluid_only(fo, o.flags)) < tol
+    assert rel_l2(gpu_pre(g, "h"), fluid_only(ho, o.flags)) < tol
+    red = g.reduce(group=1, columns=[5, 150])
+    _, _, flux = o.pre(with_flux=True)
+    lk = o.links()
+    assert red[2] == pytest.approx(flux[lk["group"] == 1].sum(), rel=max(tol, 1e-10) * 10)
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_cumulant_d3q27_tgv(L, oracle, storage, tol):
+    rho, u, H = W.taylor_green_3d(12, 0.04)
+    g, o = pair(L, oracle, Q=27, dims=(12, 12, 12), storage=storage, with_ns=True, nu=0.01, k=0.02, H0=H,
+                u_init=u, rho0=rho, relax_h="1st", cu_f=True, cu_h=True)
+    g.step(40)
+    o.step(40)
+    fo, ho = o.pre()
+    assert rel_l2(gpu_pre(g, "f"), fo) < tol
+    assert rel_l2(gpu_pre(g, "h"), ho) < tol
+
+
+@pytest.mark.parametrize("storage,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_cumulant_d3q27_sphere_inlet_outlet(L, oracle, storage, tol):
+    nx, ny, nz = 20, 14, 12
+    flags, q, groups = W.sphere_box(nx, ny, nz, (9.3, 6.6, 5.8), 3.4, inlet=True)
+    n = nx * ny * nz
+    u = np.zeros((3, n))
+    u[0] = 0.02
+    H0 = 1 + 0.1 * np.random.default_rng(61).uniform(size=n)
+    g, o = pair(L, oracle, Q=27, dims=(nx, ny, nz), storage=storage, with_ns=True, nu=0.03, k=0.02, flags=flags,
+                q=q, groups=groups, H0=H0, u_init=u, rho0=np.ones(n), cu_f=True)
+    g.step(25)
+    o.step(25)
+    fo, ho = o.pre()
+    assert rel_l2(gpu_pre(g, "f"), fluid_only(fo, o.flags)) < tol
+    assert rel_l2(gpu_pre(g, "h"), fluid_only(ho, o.flags)) < tol
+
+
+def test_cumulant_aa_equals_ab(L):
+    """In-place layout with the cumulant kernels, bit for bit.  The cumulant
+    transform normalises by the zeroth moment, so the energy field is offset
+    to stay away from zero."""
+    flags, q, groups, u, rho0, H0 = W.boundary_mix()
+    groups = [dict(g, H_w=g["H_w"] + 10.0) for g in groups]
+    H0 = H0 + 10.0
+    uu = f32(u)
+
+    def make(stream):
+        g = L.LBM(9, 33, 40, storage="fp32", with_ns=True, nu=0.04, k=0.05, flags=flags, q=q, groups=groups,
+                  stream=stream, relax_h="1st", cumulant_f=True, cumulant_h=True)
+        g.set_velocity(uu)
+        g.init(H0, u=uu, rho=rho0)
+        return g
+
+    ab, aa = make(L.STREAM_AB), make(L.STREAM_AA)
+    for k in (1, 2, 19):
+        ab.step(k)
+        aa.step(k)
+        for lat in ("f", "h"):
+            assert np.array_equal(gpu_pre(ab, lat), gpu_pre(aa, lat)), (k, lat)
+            assert np.array_equal(gpu_post(ab, lat), gpu_post(aa, lat)), (k, lat)
+
+
+def test_cumulant_fp16_dev(L, oracle):
+    flags, q, groups, u, rho0, H0 = W.heated_cylinder(96, 48, 6.5, cx=24, cy=24, u_in=0.04, amp=1e-3, seed=0)
+    g, o = pair(L, oracle, Q=9, dims=(96, 48, 1), storage="fp16_dev", with_ns=True, nu=0.04, k=0.06, uvel=u,
+                flags=flags, q=q, groups=groups, H0=H0, u_init=f32(u), rho0=rho0, cu_f=True, cu_h=True,
+                relax_h="1st", rho_ref=1.0, H_ref=10.0)
+    g.step(100)
+    o.step(100)
+    fo, ho = o.pre()
+    ef = rel_l2(gpu_pre(g, "f"), fluid_only(fo, o.flags))
+    eh = rel_l2(gpu_pre(g, "h"), fluid_only(ho, o.flags))
+    print("cumulant FP16-dev vs FP64 oracle after 100 steps: f %.2e, h %.2e" % (ef, eh))
+    assert ef < 2e-4 and eh < 2e-4
+
+
+def test_cumulant_adjoint_unsupported(L):
+    import torch
+    g = L.LBM(9, 8, 8, k=0.01, with_source=True, relax_h="1st", cumulant_h=True)
+    lam = torch.zeros(9, 64, dtype=torch.float32, device=g.device)
+    with pytest.raises(L.LBMError) as e:
+        g.adjoint_step(lam, torch.empty_like(lam))
+    assert e.value.status == L.EUNSUPPORTED
