@@ -182,7 +182,7 @@ def leg_adjoint(torch, L, np, n1=512, steps=2000, interval=45):
     return out
 
 
-def cpu_baseline(inputs, steps):
+def cpu_baseline(inputs, steps, single_thread=True):
     from oracle import oracle as O
 
     flags, q, groups, u, rho0, H0, nx, ny, nu, k = inputs
@@ -193,10 +193,19 @@ def cpu_baseline(inputs, steps):
     t0 = time.perf_counter()
     o.step(steps)
     sec = time.perf_counter() - t0
-    return {"value": nx * ny * steps / sec / 1e6, "unit": "MLUPS", "cores": int(O.lib().ora_threads()),
-            "kind": "oracle",
-            "sample": f"{steps} steps of the same {nx}x{ny} coupled workload, FP64 oracle "
-                      f"({sec:.1f} s)"}
+    cores = int(O.lib().ora_threads())
+    out = {"value": nx * ny * steps / sec / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "sample": f"{steps} steps of the same {nx}x{ny} coupled workload, FP64 oracle ({sec:.1f} s)"}
+    if single_thread:
+        # one more step on one thread (the OpenMP node loop is the only parallelism)
+        O.lib().ora_set_threads(1)
+        t0 = time.perf_counter()
+        o.step(1)
+        sec1 = time.perf_counter() - t0
+        O.lib().ora_set_threads(cores)
+        out["single_thread_value"] = nx * ny / sec1 / 1e6
+        out["single_thread_sample"] = f"1 step of the same workload on 1 thread ({sec1:.1f} s)"
+    return out
 
 
 def main():
@@ -211,6 +220,7 @@ def main():
                     help="population layout: in place (aa, measured faster for D2Q9 FP32) or two arrays (ab)")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu-single", action="store_true", help="skip the single-thread oracle step")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP16, D3Q27 and adjoint legs")
     ap.add_argument("--extra-scale", type=float, default=1.0, help="scale the step counts of those legs")
     args = ap.parse_args()
@@ -317,7 +327,7 @@ def main():
         out["adjoint_forward_ratio"] = out["adjoint"]["no_replay"]["ratio"]
     if not args.no_cpu:
         inputs = (flags, q, groups, uf.astype(np.float64), rho0, H0, nx, ny, nu, k)
-        out["cpu_baseline"] = cpu_baseline(inputs, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(inputs, args.cpu_steps, not args.no_cpu_single)
     print(json.dumps(out), flush=True)
 
 

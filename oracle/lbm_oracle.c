@@ -51,6 +51,18 @@ int ora_threads(void) {
 #endif
 }
 
+/* Sets the threads the node loops use (timing only; results do not depend on
+ * it).  Returns the previous count. */
+int ora_set_threads(int n) {
+  const int prev = ora_threads();
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+  return prev;
+}
+
 /* ---------------------------------------------------------------------------
  * Velocity sets and moment orders.
  * D3Q27 velocities in the paper's order (Sec. 2.1, vectors e_x, e_y, e_z).
