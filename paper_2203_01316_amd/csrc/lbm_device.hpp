@@ -82,26 +82,35 @@ struct StoreT;
 // Loads and stores of the population arrays.  Each stored element is written
 // once per step and read back only in the next one, so stores bypass the
 // caches (non-temporal); loads are ordinary (measured faster on MI355X).
+// P: a pointer to the element type, generic or global address space.
 template <>
 struct StoreT<double> {
-  __device__ static double ld(const double *p) { return *p; }
-  __device__ static void st(double *p, double v) { __builtin_nontemporal_store(v, p); }
+  template <class P>
+  __device__ static double ld(P p) { return *p; }
+  template <class P>
+  __device__ static void st(P p, double v) { __builtin_nontemporal_store(v, p); }
 };
 template <>
 struct StoreT<float> {
-  __device__ static float ld(const float *p) { return *p; }
-  __device__ static void st(float *p, float v) { __builtin_nontemporal_store(v, p); }
+  template <class P>
+  __device__ static float ld(P p) { return *p; }
+  template <class P>
+  __device__ static void st(P p, float v) { __builtin_nontemporal_store(v, p); }
 };
 template <>
 struct StoreT<__half> {
-  __device__ static float ld(const __half *p) {
-    unsigned short b = *reinterpret_cast<const unsigned short *>(p);
-    return __half2float(__ushort_as_half(b));
+  __device__ static float ld(const __half *p) { return ld_bits(*reinterpret_cast<const unsigned short *>(p)); }
+  __device__ static float ld(const __attribute__((address_space(1))) __half *p) {
+    return ld_bits(*reinterpret_cast<const __attribute__((address_space(1))) unsigned short *>(p));
   }
   __device__ static void st(__half *p, float v) {
-    unsigned short b = __half_as_ushort(__float2half_rn(v));
-    __builtin_nontemporal_store(b, reinterpret_cast<unsigned short *>(p));
+    __builtin_nontemporal_store(st_bits(v), reinterpret_cast<unsigned short *>(p));
   }
+  __device__ static void st(__attribute__((address_space(1))) __half *p, float v) {
+    __builtin_nontemporal_store(st_bits(v), reinterpret_cast<__attribute__((address_space(1))) unsigned short *>(p));
+  }
+  __device__ static float ld_bits(unsigned short b) { return __half2float(__ushort_as_half(b)); }
+  __device__ static unsigned short st_bits(float v) { return __half_as_ushort(__float2half_rn(v)); }
 };
 
 // Rest-equilibrium weight of direction i (product of 1-D weights 2/3, 1/6).

@@ -458,6 +458,18 @@ static lbm_status activate(lbm_ctx *ctx) {
   return LBM_OK;
 }
 
+// Multiplier and shift for exact division of node indices (below 2^31) by d:
+// with s = 31 + ceil(log2 d) and M = ceil(2^s / d) < 2^32, floor(m M / 2^s) =
+// floor(m / d), since M d - 2^s < d <= 2^(s - 31) bounds the error of m M / 2^s
+// against m / d below 1 / d (Granlund and Montgomery, division by invariant
+// integers using multiplication, 1994).
+static void divisor_magic(uint32_t d, uint32_t *M, int32_t *s) {
+  int l = 0;
+  while (((uint64_t)1 << l) < d) l++;
+  *s = 31 + l;
+  *M = (uint32_t)((((uint64_t)1 << *s) + d - 1) / d);
+}
+
 static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   KArgs a;
   memset(&a, 0, sizeof(a));
@@ -484,6 +496,8 @@ static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   a.nx = ctx->p.nx;
   a.ny = ctx->p.ny;
   a.nz = ctx->p.nz;
+  divisor_magic((uint32_t)a.nx, &a.div_nx, &a.sh_nx);
+  divisor_magic((uint32_t)a.ny, &a.div_ny, &a.sh_ny);
   // block orders measured best on MI355X: D2Q9 tiles rows per XCD; D2Q9
   // FP16 planes one slab per XCD (dispatch order in the streamed AA phase);
   // D3Q27 dispatch order

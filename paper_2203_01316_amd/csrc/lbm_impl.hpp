@@ -81,17 +81,53 @@ __device__ __forceinline__ constexpr int tile_pos(int s) {
 }
 
 // NL: lattices per tile (1 or 2) when the caller knows it at compile time,
-// else 0 and ps holds the slots per tile.
+// else 0 and ps holds the slots per tile.  A population's element index is
+// slot_offset(slot) + node_offset(m): the first is uniform over a wavefront
+// (it folds into the scalar base address), the second is shared by the slots
+// pulled from one node.  Node indices are below 2^31 (the host rejects larger
+// lattices), and (m / T) x (slots per tile) stays below 2^32 for every tile.
+template <int Q, class S>
+__device__ __forceinline__ int64_t slot_offset(int slot, int64_t ps) {
+  if constexpr (sizeof(S) == 2)
+    return (int64_t)slot * ps;
+  else
+    return (int64_t)tile_pos<Q>(slot) * (pop_tile_bytes(Q) / (int)sizeof(S));
+}
+
+template <int Q, class S, int NL>
+__device__ __forceinline__ uint64_t node_offset(int64_t ps, int64_t m) {
+  const uint32_t u = (uint32_t)m;
+  if constexpr (sizeof(S) == 2) {
+    return u;
+  } else {
+    constexpr uint32_t T = pop_tile_bytes(Q) / sizeof(S);
+    const uint32_t spt = NL ? (uint32_t)(Q * NL) : (uint32_t)ps;
+    uint64_t o = (uint64_t)((u / T) * spt) * T + (u % T);
+    // one 64-bit value per pulled node, added once per access (the compiler
+    // would otherwise split the sum and redo the 64-bit adds per slot)
+    asm("" : "+v"(o));
+    return o;
+  }
+}
+
+// Base address of one slot, as a global-memory pointer.  Every caller passes
+// a kernel-argument base and a slot fixed by an unrolled direction loop, so
+// the address is uniform over the wavefront; the empty asm keeps it as one
+// scalar value instead of letting the compiler fold the slot's constant
+// offset into per-lane adds.
+template <class E>
+using global_ptr = __attribute__((address_space(1))) E *;
+
+template <class E>
+__device__ __forceinline__ global_ptr<E> uniform_base(E *p) {
+  uint64_t v = reinterpret_cast<uint64_t>(p);
+  asm("" : "+s"(v));
+  return (global_ptr<E>)v;
+}
+
 template <int Q, class S, int NL>
 __device__ __forceinline__ int64_t pop_index(int slot, int64_t ps, int64_t m) {
-  if constexpr (sizeof(S) == 2) {
-    return (int64_t)slot * ps + m;
-  } else {
-    constexpr uint64_t T = pop_tile_bytes(Q) / sizeof(S);
-    const uint64_t spt = NL ? (uint64_t)(Q * NL) : (uint64_t)ps;
-    const uint64_t u = (uint64_t)m;
-    return (int64_t)(((u / T) * spt + (uint64_t)tile_pos<Q>(slot)) * T + (u % T));
-  }
+  return slot_offset<Q, S>(slot, ps) + (int64_t)node_offset<Q, S, NL>(ps, m);
 }
 
 // Load / store population i (stored in slot `slot`) of node m; ps is the
@@ -102,8 +138,9 @@ __device__ __forceinline__ typename StT<ST>::R ldp(const void *base, int slot, i
                                                    typename StT<ST>::R ref) {
   using T = StT<ST>;
   using R = typename T::R;
-  const typename T::S *p = static_cast<const typename T::S *>(base) + pop_index<Q, typename T::S, NL>(slot, ps, m);
-  R v = StoreT<typename T::S>::ld(p);
+  const global_ptr<const typename T::S> p =
+      uniform_base(static_cast<const typename T::S *>(base) + slot_offset<Q, typename T::S>(slot, ps));
+  R v = StoreT<typename T::S>::ld(p + node_offset<Q, typename T::S, NL>(ps, m));
   if constexpr (T::DEV) v += weight<Q, R>(slot) * ref;
   return v;
 }
@@ -113,8 +150,9 @@ __device__ __forceinline__ void stp(void *base, int slot, int64_t ps, int64_t m,
                                     typename StT<ST>::R ref) {
   using T = StT<ST>;
   if constexpr (T::DEV) v -= weight<Q, typename T::R>(slot) * ref;
-  typename T::S *p = static_cast<typename T::S *>(base) + pop_index<Q, typename T::S, NL>(slot, ps, m);
-  StoreT<typename T::S>::st(p, v);
+  const global_ptr<typename T::S> p =
+      uniform_base(static_cast<typename T::S *>(base) + slot_offset<Q, typename T::S>(slot, ps));
+  StoreT<typename T::S>::st(p + node_offset<Q, typename T::S, NL>(ps, m), v);
 }
 
 // Value a store followed by a load of population i would return.
@@ -148,26 +186,62 @@ __device__ __forceinline__ const float *rates<float>(const KArgs &a, bool f) {
 
 __device__ __forceinline__ int wrapm(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Coordinates of a node and the index parts of its neighbours: node
+// (x + dx, y + dy, z + dz), wrapped periodically, has index
+// X[dx + 1] + Y[dy + 1] + Z[dz + 1].
 struct Node {
   int x, y, z;
+  uint32_t X[3], Y[3], Z[3];
 };
 
-__device__ __forceinline__ Node coords(const KArgs &a, int64_t m) {
+// floor(m / d) for m < 2^31 from the divisor's multiplier M and shift s (set
+// on the host): M = ceil(2^s / d), s = 31 + ceil(log2 d).
+__device__ __forceinline__ uint32_t div_magic(uint32_t m, uint32_t M, int s) {
+  return (uint32_t)(((uint64_t)m * M) >> s);
+}
+
+__device__ __forceinline__ uint32_t wrap_lo(uint32_t v, uint32_t n) { return v == 0 ? n - 1 : v - 1; }
+__device__ __forceinline__ uint32_t wrap_hi(uint32_t v, uint32_t n) { return v + 1 == n ? 0 : v + 1; }
+
+template <int Q>
+__device__ __forceinline__ Node coords(const KArgs &a, int64_t m64) {
+  const uint32_t m = (uint32_t)m64;
+  const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny;
+  const uint32_t r = div_magic(m, a.div_nx, a.sh_nx);
+  uint32_t y = r, z = 0;
+  if constexpr (Lat<Q>::D == 3) {
+    z = div_magic(r, a.div_ny, a.sh_ny);
+    y = r - z * ny;
+  }
+  const uint32_t x = m - r * nx;
   Node c;
-  c.x = (int)(m % a.nx);
-  const int64_t r = m / a.nx;
-  c.y = (int)(r % a.ny);
-  c.z = (int)(r / a.ny);
+  c.x = (int)x;
+  c.y = (int)y;
+  c.z = (int)z;
+  c.X[0] = wrap_lo(x, nx);
+  c.X[1] = x;
+  c.X[2] = wrap_hi(x, nx);
+  c.Y[0] = wrap_lo(y, ny) * nx;
+  c.Y[1] = y * nx;
+  c.Y[2] = wrap_hi(y, ny) * nx;
+  if constexpr (Lat<Q>::D == 3) {
+    const uint32_t nxy = nx * ny, nz = (uint32_t)a.nz;
+    c.Z[0] = wrap_lo(z, nz) * nxy;
+    c.Z[1] = z * nxy;
+    c.Z[2] = wrap_hi(z, nz) * nxy;
+  } else {
+    c.Z[0] = c.Z[1] = c.Z[2] = 0;
+  }
   return c;
 }
 
 // node x + sign * e_i with periodic wrap
 template <int Q>
-__device__ __forceinline__ int64_t shifted(const KArgs &a, Node c, int i, int sign) {
-  const int xs = wrapm(c.x + sign * Lat<Q>::ex(i), a.nx);
-  const int ys = wrapm(c.y + sign * Lat<Q>::ey(i), a.ny);
-  const int zs = wrapm(c.z + sign * Lat<Q>::ez(i), a.nz);
-  return xs + (int64_t)a.nx * (ys + (int64_t)a.ny * zs);
+__device__ __forceinline__ int64_t shifted(const KArgs &a, const Node &c, int i, int sign) {
+  (void)a;
+  uint32_t m = c.X[1 + sign * Lat<Q>::ex(i)] + c.Y[1 + sign * Lat<Q>::ey(i)];
+  if constexpr (Lat<Q>::D == 3) m += c.Z[1 + sign * Lat<Q>::ez(i)];
+  return (int64_t)m;
 }
 
 // Prescribed velocity at node m (field or uniform).
@@ -420,7 +494,7 @@ __device__ __forceinline__ void bulk_node(const KArgs &a, int64_t m) {
   if (m >= a.n) return;
   uint8_t cl = CLS_BULK;
   if constexpr (GEOM) cl = a.cls[m];
-  const Node c = coords(a, m);
+  const Node c = coords<Q>(a, m);
   R f[Q], h[Q];
 #pragma unroll
   for (int i = 0; i < Q; i++) {
@@ -476,7 +550,7 @@ __device__ __forceinline__ void pull_links(const KArgs &a, int64_t m, int32_t lb
                                            typename StT<ST>::R *f, typename StT<ST>::R *h, double *flux) {
   using R = typename StT<ST>::R;
   constexpr bool AB = LAY == LAY_AB;
-  const Node c = coords(a, m);
+  const Node c = coords<Q>(a, m);
   const R fref = R(a.fref), href = R(a.href);
 #pragma unroll
   for (int i = 0; i < Q; i++) {
@@ -597,7 +671,7 @@ __device__ __forceinline__ void special_node(const KArgs &a, int64_t t) {
   if (t >= a.nspecial) return;
   const DevSpecial sp = a.special[t];
   const int64_t m = sp.node;
-  const Node c = coords(a, m);
+  const Node c = coords<Q>(a, m);
   double *flux = MODE == MODE_MACRO ? a.link_flux : nullptr;
   R f[Q], h[Q];
   if (sp.type == NODE_EQ) {
@@ -618,7 +692,7 @@ __device__ __forceinline__ void special_node(const KArgs &a, int64_t t) {
         }
       }
       if constexpr (AA) {
-        finish_node<Q, ST, NS, MODE, LAY, CU>(a, coords(a, up), up, fu, hu);
+        finish_node<Q, ST, NS, MODE, LAY, CU>(a, coords<Q>(a, up), up, fu, hu);
         if constexpr (MODE == MODE_STEP) save_side<Q, ST, NS>(a, sp.ub, sp.umask, 2 * t + 1, fu, hu);
       }
     }
@@ -663,7 +737,7 @@ __global__ void __launch_bounds__(64) k_side(const KArgs a) {
   for (int k = 0; k < 2; k++) {
     if (k == 1 && sp.type != NODE_OUTLET) break;
     const int64_t m = k == 0 ? sp.node : (sp.node % a.nx == 0 ? sp.node + a.nx - 1 : sp.node - 1);
-    const Node c = coords(a, m);
+    const Node c = coords<Q>(a, m);
     R f[Q], h[Q];
 #pragma unroll
     for (int i = 0; i < Q; i++) {
@@ -730,7 +804,7 @@ __global__ void __launch_bounds__(256) k_convert(const KArgs a, const void *from
   using R = typename StT<ST>::R;
   const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (m >= a.n) return;
-  const Node c = coords(a, m);
+  const Node c = coords<Q>(a, m);
   const bool solid = a.cls && a.cls[m] == CLS_SOLID;
 #pragma unroll
   for (int i = 0; i < Q; i++) {
@@ -754,7 +828,7 @@ __global__ void __launch_bounds__(256) k_adjoint(const KArgs a, const R *lam_nex
   constexpr int D = Lat<Q>::D;
   const int64_t m = tile_of(a, blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   if (m >= a.n) return;
-  const Node c = coords(a, m);
+  const Node c = coords<Q>(a, m);
   R g[Q];
 #pragma unroll
   for (int i = 0; i < Q; i++) {
@@ -840,11 +914,28 @@ static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b -
       return hipErrorInvalidValue;            \
   }
 
+// Residency cap of a step kernel.  The step kernels use no LDS; an unused
+// dynamic LDS request caps the blocks of 256 threads resident on one CU (160
+// KB of LDS) at `blocks`.  On MI355X two FP32 two-array steps stream faster
+// under a cap than at the residency their register count allows: D3Q27 at 2
+// blocks per CU (about 1.5% at 256^3) and D2Q9 at 3 (about 4% at 2048^2),
+// both with the central-moment collision.  The AA layout and the other storage
+// types measured no gain, the D3Q27 cumulant step a loss.  0 = no cap.
+constexpr size_t lds_for_blocks(int blocks) { return (size_t)(160 * 1024) / (blocks + 1) + 1024; }
+
+template <int Q, int ST, int LAY, int CU>
+constexpr size_t step_lds() {
+  constexpr bool fp32_ab = (ST == ST_FP32 || ST == ST_FP32_DEV) && LAY == LAY_AB && CU == 0;
+  if constexpr (Q == 27 && fp32_ab) return lds_for_blocks(2);
+  if constexpr (Q == 9 && fp32_ab) return lds_for_blocks(3);
+  return 0;
+}
+
 template <int Q, int ST, bool NS, bool GEOM, int LAY>
 static hipError_t pass_t(int mode, int cu, const KArgs &a, hipStream_t s) {
   const unsigned g = blocks_for(a.n, 256);
   if (mode == MODE_STEP)
-    LBM_DISPATCH_CU(NS, cu, (k_bulk<Q, ST, NS, GEOM, MODE_STEP, LAY, CU><<<g, 256, 0, s>>>(a)))
+    LBM_DISPATCH_CU(NS, cu, (k_bulk<Q, ST, NS, GEOM, MODE_STEP, LAY, CU><<<g, 256, step_lds<Q, ST, LAY, CU>(), s>>>(a)))
   else if (mode == MODE_PRE)
     k_bulk<Q, ST, NS, GEOM, MODE_PRE, LAY><<<g, 256, 0, s>>>(a);
   else
@@ -868,7 +959,7 @@ static hipError_t special_t(int mode, int cu, const KArgs &a, hipStream_t s) {
 template <int Q, int ST, bool NS, int LAY>
 static hipError_t fused_t(int cu, const KArgs &a, hipStream_t s) {
   const int sblocks = (int)((blocks_for(a.nspecial, 256) + 7) / 8 * 8);
-  LBM_DISPATCH_CU(NS, cu, (k_fused<Q, ST, NS, LAY, CU><<<blocks_for(a.n, 256) + sblocks, 256, 0, s>>>(a, sblocks)))
+  LBM_DISPATCH_CU(NS, cu, (k_fused<Q, ST, NS, LAY, CU><<<blocks_for(a.n, 256) + sblocks, 256, step_lds<Q, ST, LAY, CU>(), s>>>(a, sblocks)))
   return hipGetLastError();
 }
 

@@ -99,6 +99,8 @@ struct KArgs {
   int64_t n;
   int64_t ps;              // population layout: slots per tile, or the FP16 plane stride
   int32_t nx, ny, nz;
+  uint32_t div_nx, div_ny; // division by nx and ny (multiplier and shift, see
+  int32_t sh_nx, sh_ny;    // div_magic in lbm_impl.hpp)
   int32_t with_uvel;       // advection velocity from the field (else u0)
   int32_t tilemap;         // block -> tile order: 0 one slab per XCD, 1 rows per XCD,
                            // 2 dispatch order
