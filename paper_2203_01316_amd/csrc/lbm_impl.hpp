@@ -80,6 +80,15 @@ __device__ __forceinline__ constexpr int tile_pos(int s) {
   return ((Lat<Q>::ez(s) + 1) * 3 + (Lat<Q>::ey(s) + 1)) * 3 + (Lat<Q>::ex(s) + 1) - (Lat<Q>::D == 2 ? 9 : 0);
 }
 
+// Direction whose slot sits at tile position k, so that k = 0 .. Q-1 visits
+// the slots of a tile in address order.
+template <int Q>
+__device__ __forceinline__ constexpr int dir_at_pos(int k) {
+  for (int i = 0; i < Q; i++)
+    if (tile_pos<Q>(i) == k) return i;
+  return 0;
+}
+
 // NL: lattices per tile (1 or 2) when the caller knows it at compile time,
 // else 0 and ps holds the slots per tile.  A population's element index is
 // slot_offset(slot) + node_offset(m): the first is uniform over a wavefront
@@ -326,6 +335,17 @@ __device__ __forceinline__ void post_addr(const KArgs &a, Node c, int64_t m, int
   }
 }
 
+// Access order of a bulk node.  D3Q27 central-moment steps pull all of f and
+// then all of h, and store, each in address order within a tile: f's
+// collision then waits only for f's loads while h's are still in flight.  On
+// MI355X this measured 1.7% faster at 256^3 (FP32 and FP16-dev); the D2Q9 and
+// cumulant steps keep direction order with f and h interleaved, which
+// measured as fast or faster for them.
+template <int Q, int CU>
+__device__ __forceinline__ constexpr bool split_order() {
+  return Lat<Q>::D == 3 && CU == 0;
+}
+
 // ---------------------------------------------------------------------------
 // Epilogue: pre-collision populations f, h (direction order) of node m ->
 // collide and store (f, h then hold the stored post-collision values), or
@@ -354,7 +374,8 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
       else
         collide<D, R>(g, rates<R>(a, true), ux, uy, uz, R(0));
 #pragma unroll
-      for (int i = 0; i < Q; i++) {
+      for (int k = 0; k < Q; k++) {
+        const int i = split_order<Q, CU>() ? dir_at_pos<Q>(k) : k;
         int sl;
         int64_t nd;
         store_addr<Q, LAY>(a, c, m, i, sl, nd);
@@ -369,7 +390,8 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
     else
       collide<D, R>(g, rates<R>(a, false), ux, uy, uz, src);
 #pragma unroll
-    for (int i = 0; i < Q; i++) {
+    for (int k = 0; k < Q; k++) {
+      const int i = split_order<Q, CU>() ? dir_at_pos<Q>(k) : k;
       int sl;
       int64_t nd;
       store_addr<Q, LAY>(a, c, m, i, sl, nd);
@@ -496,13 +518,34 @@ __device__ __forceinline__ void bulk_node(const KArgs &a, int64_t m) {
   if constexpr (GEOM) cl = a.cls[m];
   const Node c = coords<Q>(a, m);
   R f[Q], h[Q];
+  if constexpr (split_order<Q, CU>()) {
+    if constexpr (NS) {
 #pragma unroll
-  for (int i = 0; i < Q; i++) {
-    int sl;
-    int64_t nd;
-    pull_addr<Q, LAY>(a, c, m, i, sl, nd);
-    if constexpr (NS) f[i] = ldp<Q, ST, NS ? 2 : 1>(a.fsrc, sl, a.ps, nd, R(a.fref));
-    h[i] = ldp<Q, ST, NS ? 2 : 1>(a.hsrc, sl, a.ps, nd, R(a.href));
+      for (int k = 0; k < Q; k++) {
+        const int i = dir_at_pos<Q>(k);
+        int sl;
+        int64_t nd;
+        pull_addr<Q, LAY>(a, c, m, i, sl, nd);
+        f[i] = ldp<Q, ST, NS ? 2 : 1>(a.fsrc, sl, a.ps, nd, R(a.fref));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < Q; k++) {
+      const int i = dir_at_pos<Q>(k);
+      int sl;
+      int64_t nd;
+      pull_addr<Q, LAY>(a, c, m, i, sl, nd);
+      h[i] = ldp<Q, ST, NS ? 2 : 1>(a.hsrc, sl, a.ps, nd, R(a.href));
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      int sl;
+      int64_t nd;
+      pull_addr<Q, LAY>(a, c, m, i, sl, nd);
+      if constexpr (NS) f[i] = ldp<Q, ST, NS ? 2 : 1>(a.fsrc, sl, a.ps, nd, R(a.fref));
+      h[i] = ldp<Q, ST, NS ? 2 : 1>(a.hsrc, sl, a.ps, nd, R(a.href));
+    }
   }
   if constexpr (GEOM) {
     if (__ballot(cl == CLS_OUTLET)) {
