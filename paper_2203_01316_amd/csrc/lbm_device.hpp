@@ -314,12 +314,30 @@ template <int D>
 __host__ __device__ constexpr int cm_slot(int m, int n, int o) { return D == 2 ? m * 3 + n : m * 9 + n * 3 + o; }
 __host__ __device__ constexpr int binom2(int n, int k) { return (n == 2 && k == 1) ? 2 : 1; }
 
+template <int D>
+__host__ __device__ constexpr int cm_order(int k) { return cm_x<D>(k) + cm_y<D>(k) + cm_z<D>(k); }
+// Equilibrium cumulant about u of index k > 0: cs^2 at 200/020/002, else 0.
+template <int D>
+__host__ __device__ constexpr bool cu_pure2(int k) {
+  return cm_order<D>(k) == 2 && (cm_x<D>(k) == 2 || cm_y<D>(k) == 2 || cm_z<D>(k) == 2);
+}
+// With every cumulant above order K relaxed at rate 1 (K > 0), the post-
+// collision cumulant of index k is its equilibrium; true where that is zero.
+template <int D, int K>
+__host__ __device__ constexpr bool cu_post_zero(int k) {
+  return K > 0 && cm_order<D>(k) > K && !cu_pure2<D>(k);
+}
+
 // FWD: c[k] (k > 0) from mu; else mu[k] (k > 0) from c.  mu[0] = 1.
-template <int D, bool FWD, class R>
+// K > 0: every cumulant above order K relaxes at rate 1, so the forward pass
+// stops at order K and the inverse pass drops the terms whose cumulant is
+// then zero (each such term would add a signed zero).
+template <int D, bool FWD, class R, int K = 0>
 __device__ __forceinline__ void cumulant_recursion(R *mu, R *c) {
   constexpr int NQ = D == 2 ? 9 : 27;
 #pragma unroll
   for (int t = 1; t <= 2 * D; t++) {
+    if (FWD && K > 0 && t > K) break;
 #pragma unroll
     for (int k = 1; k < NQ; k++) {
       const int m = cm_x<D>(k), n = cm_y<D>(k), o = cm_z<D>(k);
@@ -335,8 +353,10 @@ __device__ __forceinline__ void cumulant_recursion(R *mu, R *c) {
           for (int e = 0; e < (D == 3 ? 3 : 1); e++) {
             if (a > pm || b > pn || e > po) continue;
             if (FWD && a == pm && b == pn && e == po) continue;
+            const int ci = cm_slot<D>(a + jx, b + jy, e + jz);
+            if (!FWD && cu_post_zero<D, K>(ci)) continue;
             const R B = R(binom2(pm, a) * binom2(pn, b) * binom2(po, e));
-            const R term = B * mu[cm_slot<D>(pm - a, pn - b, po - e)] * c[cm_slot<D>(a + jx, b + jy, e + jz)];
+            const R term = B * mu[cm_slot<D>(pm - a, pn - b, po - e)] * c[ci];
             acc = FWD ? acc - term : acc + term;
           }
       if (FWD)
@@ -347,7 +367,9 @@ __device__ __forceinline__ void cumulant_recursion(R *mu, R *c) {
   }
 }
 
-template <int D, class R>
+// K > 0: the rates of every cumulant above order K are 1 (the caller checks),
+// which those cumulants then reach exactly; K = 0: no assumption.
+template <int D, class R, int K = 0>
 __device__ __forceinline__ void collide_cu(R *g, const R *s, R ux, R uy, R uz, R src) {
   constexpr int NQ = D == 2 ? 9 : 27;
   to_central<D, R>(g, ux, uy, uz);
@@ -358,16 +380,18 @@ __device__ __forceinline__ void collide_cu(R *g, const R *s, R ux, R uy, R uz, R
   for (int k = 1; k < NQ; k++) g[k] *= inv;
   R c[NQ];
   c[0] = k0;
-  cumulant_recursion<D, true, R>(g, c);
+  cumulant_recursion<D, true, R, K>(g, c);
 #pragma unroll
   for (int k = 1; k < NQ; k++) {
-    const int m = cm_x<D>(k), n = cm_y<D>(k), o = cm_z<D>(k);
-    const bool var = (m + n + o == 2) && (m == 2 || n == 2 || o == 2);
-    c[k] = c[k] + s[k] * ((var ? R(1) / R(3) : R(0)) - c[k]);
+    const R eq = cu_pure2<D>(k) ? R(1) / R(3) : R(0);
+    if (K > 0 && cm_order<D>(k) > K)
+      c[k] = eq;
+    else
+      c[k] = c[k] + s[k] * (eq - c[k]);
   }
   const R psi = k0 + R(0.5) * src;
   const R c0 = k0 + s[0] * (psi - k0) + (R(1) - R(0.5) * s[0]) * src;
-  cumulant_recursion<D, false, R>(g, c);
+  cumulant_recursion<D, false, R, K>(g, c);
   g[0] = c0;
 #pragma unroll
   for (int k = 1; k < NQ; k++) g[k] *= c0;

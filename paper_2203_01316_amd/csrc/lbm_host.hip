@@ -416,6 +416,8 @@ struct lbm_ctx {
   const void *src;
   double sf[27], sh[27];  // moment order of the header
   double sfc[27], shc[27];  // chimera order
+  int cu_kernel;            // collision selector of the step kernels (cumulant bits,
+                            // plus 4 when the order-limited cumulant transform applies)
   int64_t t;
   std::string err;
   std::vector<DevLink> host_links;
@@ -468,6 +470,17 @@ static void divisor_magic(uint32_t d, uint32_t *M, int32_t *s) {
   while (((uint64_t)1 << l) < d) l++;
   *s = 31 + l;
   *M = (uint32_t)((((uint64_t)1 << *s) + d - 1) / d);
+}
+
+// Highest total order m + n + o among the moments k > 0 whose rate (chimera
+// order) is not 1.
+static int top_rate_order(int Q, const double *sc) {
+  int top = 0;
+  for (int k = 1; k < Q; k++) {
+    const int m = Q == 9 ? k / 3 : k / 9, n = Q == 9 ? k % 3 : (k / 3) % 3, o = Q == 9 ? 0 : k % 3;
+    if (sc[k] != 1.0 && m + n + o > top) top = m + n + o;
+  }
+  return top;
 }
 
 static KArgs make_args(lbm_ctx *ctx, int src_copy) {
@@ -527,7 +540,7 @@ static lbm_status run_pass(lbm_ctx *ctx, int mode, const KArgs &a) {
   if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[ctx->ev_used], ctx->stream), "event record");
   if (mode == MODE_STEP && ctx->geom && ctx->Q == 9) {
     // bulk and boundary nodes in one launch; the boundary time is inside it
-    HIP_TRY(ctx, launch_fused(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->lay(), ctx->p.cumulant, a, ctx->stream),
+    HIP_TRY(ctx, launch_fused(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->lay(), ctx->cu_kernel, a, ctx->stream),
             "step kernel launch");
     if (timed) {
       HIP_TRY(ctx, hipEventRecord(ctx->ev[ctx->ev_used + 1], ctx->stream), "event record");
@@ -536,12 +549,12 @@ static lbm_status run_pass(lbm_ctx *ctx, int mode, const KArgs &a) {
     }
     return LBM_OK;
   }
-  HIP_TRY(ctx, launch_pass(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->geom, ctx->lay(), mode, ctx->p.cumulant, a,
+  HIP_TRY(ctx, launch_pass(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->geom, ctx->lay(), mode, ctx->cu_kernel, a,
                            ctx->stream),
           "bulk kernel launch");
   if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[ctx->ev_used + 1], ctx->stream), "event record");
   if (ctx->geom)
-    HIP_TRY(ctx, launch_special(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->lay(), mode, ctx->p.cumulant, a, ctx->stream),
+    HIP_TRY(ctx, launch_special(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->lay(), mode, ctx->cu_kernel, a, ctx->stream),
             "boundary kernel launch");
   if (timed) {
     HIP_TRY(ctx, hipEventRecord(ctx->ev[ctx->ev_used + 2], ctx->stream), "event record");
@@ -663,6 +676,12 @@ lbm_status lbm_create(const lbm_params *p, void *workspace_dev, void *hip_stream
     ctx->sfc[chimera_index(ctx->Q, m)] = ctx->sf[k];
     ctx->shc[chimera_index(ctx->Q, m)] = ctx->sh[k];
   }
+  // the cumulant transform stops at second order (f) and first order (h)
+  // when every rate above is 1 (the hydrodynamic and Cumulants-1st presets)
+  ctx->cu_kernel = p->cumulant;
+  if (p->cumulant && (!(p->cumulant & 2) || top_rate_order(ctx->Q, ctx->sfc) <= 2) &&
+      (!(p->cumulant & 1) || top_rate_order(ctx->Q, ctx->shc) <= 1))
+    ctx->cu_kernel |= 4;
   *out = ctx;
   return LBM_OK;
 }

@@ -352,7 +352,9 @@ __device__ __forceinline__ constexpr bool split_order() {
 // write them / their moments out.
 // ---------------------------------------------------------------------------
 // CU selects the collision of each lattice: bit 0 h, bit 1 f use the cumulant
-// collision (Eqs. hydro_cu_collision, H_cu_collision), else central moments.
+// collision (Eqs. hydro_cu_collision, H_cu_collision), else central moments;
+// bit 2: the cumulants above second order (f) and first order (h) have rate 1,
+// so their transform is skipped (the Cumulants-1st and hydrodynamic presets).
 template <int Q, int ST, bool NS, int MODE, int LAY, int CU = 0>
 __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, typename StT<ST>::R *f,
                                             typename StT<ST>::R *h) {
@@ -369,7 +371,9 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
     if constexpr (NS) {
 #pragma unroll
       for (int i = 0; i < Q; i++) g[Lat<Q>::slot(i)] = f[i];
-      if constexpr (CU & 2)
+      if constexpr ((CU & 2) && (CU & 4))
+        collide_cu<D, R, 2>(g, rates<R>(a, true), ux, uy, uz, R(0));
+      else if constexpr (CU & 2)
         collide_cu<D, R>(g, rates<R>(a, true), ux, uy, uz, R(0));
       else
         collide<D, R>(g, rates<R>(a, true), ux, uy, uz, R(0));
@@ -385,7 +389,9 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
     }
 #pragma unroll
     for (int i = 0; i < Q; i++) g[Lat<Q>::slot(i)] = h[i];
-    if constexpr (CU & 1)
+    if constexpr ((CU & 1) && (CU & 4))
+      collide_cu<D, R, 1>(g, rates<R>(a, false), ux, uy, uz, src);
+    else if constexpr (CU & 1)
       collide_cu<D, R>(g, rates<R>(a, false), ux, uy, uz, src);
     else
       collide<D, R>(g, rates<R>(a, false), ux, uy, uz, src);
@@ -923,52 +929,44 @@ static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b -
       return hipErrorInvalidValue;      \
   }
 
-// cu (bit 0 h, bit 1 f: cumulant collision) as a compile-time CU for CALL;
-// f bits need the hydrodynamic lattice.
+// cu (bit 0 h, bit 1 f: cumulant collision; bit 2: order-limited cumulant
+// transform) as a compile-time CU for CALL; f bits need the hydrodynamic
+// lattice, bit 2 a cumulant bit.
+#define LBM_CU_CASE(NS_VAL, V, CALL)       \
+  case V:                                   \
+    if constexpr (!((V) & 2) || NS_VAL) {   \
+      constexpr int CU = V;                 \
+      CALL;                                 \
+      break;                                \
+    } else {                                \
+      return hipErrorInvalidValue;          \
+    }
 #define LBM_DISPATCH_CU(NS_VAL, CU_VAL, CALL) \
   switch (CU_VAL) {                           \
-    case 0: {                                 \
-      constexpr int CU = 0;                   \
-      CALL;                                   \
-      break;                                  \
-    }                                         \
-    case 1: {                                 \
-      constexpr int CU = 1;                   \
-      CALL;                                   \
-      break;                                  \
-    }                                         \
-    case 2:                                   \
-      if constexpr (NS_VAL) {                 \
-        constexpr int CU = 2;                 \
-        CALL;                                 \
-        break;                                \
-      } else {                                \
-        return hipErrorInvalidValue;          \
-      }                                       \
-    case 3:                                   \
-      if constexpr (NS_VAL) {                 \
-        constexpr int CU = 3;                 \
-        CALL;                                 \
-        break;                                \
-      } else {                                \
-        return hipErrorInvalidValue;          \
-      }                                       \
+    LBM_CU_CASE(NS_VAL, 0, CALL)              \
+    LBM_CU_CASE(NS_VAL, 1, CALL)              \
+    LBM_CU_CASE(NS_VAL, 2, CALL)              \
+    LBM_CU_CASE(NS_VAL, 3, CALL)              \
+    LBM_CU_CASE(NS_VAL, 5, CALL)              \
+    LBM_CU_CASE(NS_VAL, 6, CALL)              \
+    LBM_CU_CASE(NS_VAL, 7, CALL)              \
     default:                                  \
       return hipErrorInvalidValue;            \
   }
 
 // Residency cap of a step kernel.  The step kernels use no LDS; an unused
 // dynamic LDS request caps the blocks of 256 threads resident on one CU (160
-// KB of LDS) at `blocks`.  On MI355X two FP32 two-array steps stream faster
+// KB of LDS) at `blocks`.  On MI355X the FP32 two-array steps stream faster
 // under a cap than at the residency their register count allows: D3Q27 at 2
-// blocks per CU (about 1.5% at 256^3) and D2Q9 at 3 (about 4% at 2048^2),
-// both with the central-moment collision.  The AA layout and the other storage
-// types measured no gain, the D3Q27 cumulant step a loss.  0 = no cap.
+// blocks per CU (central moments about 1.5%, order-limited cumulants 2.6% at
+// 256^3) and D2Q9 at 3 (about 3-4% at 2048^2).  The AA layout, the other
+// storage types and the full cumulant transform measured no gain or a loss.
+// 0 = no cap.
 constexpr size_t lds_for_blocks(int blocks) { return (size_t)(160 * 1024) / (blocks + 1) + 1024; }
 
 template <int Q, int ST, int LAY, int CU>
 constexpr size_t step_lds() {
-  constexpr bool fp32_ab = (ST == ST_FP32 || ST == ST_FP32_DEV) && LAY == LAY_AB && CU == 0;
+  constexpr bool fp32_ab = (ST == ST_FP32 || ST == ST_FP32_DEV) && LAY == LAY_AB && (CU == 0 || (CU & 4));
   if constexpr (Q == 27 && fp32_ab) return lds_for_blocks(2);
   if constexpr (Q == 9 && fp32_ab) return lds_for_blocks(3);
   return 0;

@@ -138,7 +138,8 @@ enum : int { ST_FP64 = 0, ST_FP32 = 1, ST_FP32_DEV = 2, ST_FP16_DEV = 3 };
 
 // Launchers; return hipSuccess or the launch error.  lay: LAY_*.  cu: the
 // collision of each lattice in MODE_STEP (bit 0 h, bit 1 f: cumulants, else
-// central moments).
+// central moments; bit 2 with a cumulant bit: every cumulant above order 2 of
+// f and above order 1 of h has rate 1).
 hipError_t launch_pass(int Q, int storage, bool ns, bool geom, int lay, int mode, int cu, const KArgs &a,
                        hipStream_t s);
 hipError_t launch_special(int Q, int storage, bool ns, int lay, int mode, int cu, const KArgs &a, hipStream_t s);

@@ -26,7 +26,7 @@ def fluid_only(arr, flags):
 
 def pair(L, O, *, Q, dims, storage="fp64", with_ns=False, relax_h="trt", nu=0.0, k=0.01, u0=(0, 0, 0),
          uvel=None, src=None, flags=None, q=None, groups=(), H0=None, u_init=None, rho0=None, oracle_init=True,
-         cu_f=False, cu_h=False, stream=0, rho_ref=0.0, H_ref=0.0):
+         cu_f=False, cu_h=False, stream=0, rho_ref=0.0, H_ref=0.0, relax_f="ns"):
     """GPU context and oracle simulation over identical inputs, both at t = 0."""
     nx, ny, nz = dims
     n = nx * ny * nz
@@ -34,7 +34,7 @@ def pair(L, O, *, Q, dims, storage="fp64", with_ns=False, relax_h="trt", nu=0.0,
     cast = f32 if lowp else (lambda a: np.asarray(a, dtype=np.float64))
     uv = None if uvel is None else cast(np.asarray(uvel).reshape(3, n))
     sr = None if src is None else cast(np.asarray(src).reshape(n))
-    kw = dict(with_ns=with_ns, storage=storage, relax_h=relax_h, relax_f="ns", nu=nu, k=k, u0=u0,
+    kw = dict(with_ns=with_ns, storage=storage, relax_h=relax_h, relax_f=relax_f, nu=nu, k=k, u0=u0,
               u_mode=1 if uv is not None and not with_ns else 0, with_source=src is not None,
               cumulant_f=cu_f, cumulant_h=cu_h, stream=stream, rho_ref=rho_ref, H_ref=H_ref)
     g = L.LBM(Q, nx, ny, nz, flags=flags, q=q, groups=groups, **kw)

@@ -101,6 +101,31 @@ def test_cumulant_d3q27_sphere_inlet_outlet(L, oracle, storage, tol):
     assert rel_l2(gpu_pre(g, "h"), fluid_only(ho, o.flags)) < tol
 
 
+@pytest.mark.parametrize("Q,dims", [(9, (33, 21, 1)), (27, (10, 9, 8))])
+@pytest.mark.parametrize("storage,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_cumulant_full_transform(L, oracle, Q, dims, storage, tol):
+    """Rates other than 1 above second order (f: one rate for every moment;
+    h: the TRT preset, odd orders at s^H).  The library then runs the
+    cumulant transform to the highest order; the presets of the other tests
+    take the order-limited transform."""
+    rng = np.random.default_rng(71)
+    n = dims[0] * dims[1] * dims[2]
+    D = 2 if Q == 9 else 3
+    u = np.zeros((3, n))
+    u[:D] = rng.uniform(-0.03, 0.03, (D, n))
+    rho = 1 + 0.01 * rng.standard_normal(n)
+    H0 = 1 + 0.1 * rng.uniform(size=n)
+    g, o = pair(L, oracle, Q=Q, dims=dims, storage=storage, with_ns=True, nu=0.02, k=0.03, H0=H0, u_init=u,
+                rho0=rho, relax_f="srt", relax_h="trt", cu_f=True, cu_h=True)
+    sf, sh = L.relaxation_rates(g.params)
+    assert np.any(sf[:Q] != 1.0) and np.any(sh[:Q] != 1.0)
+    g.step(30)
+    o.step(30)
+    fo, ho = o.pre()
+    assert rel_l2(gpu_pre(g, "f"), fo) < tol
+    assert rel_l2(gpu_pre(g, "h"), ho) < tol
+
+
 def test_cumulant_aa_equals_ab(L):
     """In-place layout with the cumulant kernels, bit for bit.  The cumulant
     transform normalises by the zeroth moment, so the energy field is offset
