@@ -140,7 +140,7 @@ void compute_rates(const lbm_params *p, double *sf, double *sh) {
 
 // Node count of a population buffer: padded to whole tiles; also the plane
 // stride of the FP16 layout.
-int64_t plane_nodes(int64_t n) { return (n + POP_PAD - 1) / POP_PAD * POP_PAD; }
+int64_t plane_nodes(int64_t n, int Q) { return (n + pop_pad(Q) - 1) / pop_pad(Q) * pop_pad(Q); }
 
 Layout layout(const lbm_params *p) {
   Layout L;
@@ -153,9 +153,9 @@ Layout layout(const lbm_params *p) {
   const size_t es = storage_size(p->storage);
   const bool planes = p->storage == LBM_FP16_DEV;
   const int nlat = p->with_ns ? 2 : 1;
-  L.pop_bytes = align_up((size_t)Q * plane_nodes(n) * es);
+  L.pop_bytes = align_up((size_t)Q * plane_nodes(n, Q) * es);
   L.region_bytes = (size_t)nlat * L.pop_bytes;
-  L.ps = planes ? plane_nodes(n) : (int64_t)Q * nlat;
+  L.ps = planes ? plane_nodes(n, Q) : (int64_t)Q * nlat;
   const int copies = p->stream == LBM_STREAM_AA ? 1 : 2;
   for (int c = 0; c < 2; c++) {
     L.off_region[c] = c < copies ? off : L.off_region[0];

@@ -10,9 +10,9 @@ namespace lbm {
 // Bytes per slot of a population tile (FP64 and FP32 storage, see
 // lbm_impl.hpp; measured best on MI355X): a tile holds pop_tile_bytes(Q) /
 // sizeof(element) consecutive nodes.  The node count of a lattice is padded
-// to a multiple of POP_PAD nodes, a multiple of every tile.
-constexpr int pop_tile_bytes(int Q) { return Q == 27 ? 4096 : 1024; }
-constexpr int POP_PAD = 4096 / 4;
+// to a multiple of pop_pad(Q) nodes, a multiple of its tiles.
+constexpr int pop_tile_bytes(int Q) { return Q == 27 ? 32768 : 1024; }
+constexpr int pop_pad(int Q) { return pop_tile_bytes(Q) / 4 > 1024 ? pop_tile_bytes(Q) / 4 : 1024; }
 
 // Device copy of one cut link; same layout as lbm_link.
 struct DevLink {
