@@ -11,7 +11,7 @@ namespace lbm {
 // lbm_impl.hpp; measured best on MI355X): a tile holds pop_tile_bytes(Q) /
 // sizeof(element) consecutive nodes.  The node count of a lattice is padded
 // to a multiple of pop_pad(Q) nodes, a multiple of its tiles.
-constexpr int pop_tile_bytes(int Q) { return Q == 27 ? 32768 : 1024; }
+constexpr int pop_tile_bytes(int Q) { return Q == 27 ? 32768 : 4096; }
 constexpr int pop_pad(int Q) { return pop_tile_bytes(Q) / 4 > 1024 ? pop_tile_bytes(Q) / 4 : 1024; }
 
 // Device copy of one cut link; same layout as lbm_link.
