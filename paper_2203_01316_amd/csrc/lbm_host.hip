@@ -511,17 +511,18 @@ static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   a.nz = ctx->p.nz;
   divisor_magic((uint32_t)a.nx, &a.div_nx, &a.sh_nx);
   divisor_magic((uint32_t)a.ny, &a.div_ny, &a.sh_ny);
-  // block orders measured best on MI355X: D2Q9 tiles rows per XCD; D2Q9
-  // FP16 planes one slab per XCD (dispatch order in the streamed AA phase);
-  // D3Q27 dispatch order
+  // block orders measured best on MI355X: D2Q9 tiles one slab per XCD in
+  // place (AA), chunks of two x-rows per XCD with two arrays (AB); D2Q9 FP16
+  // planes one slab per XCD (dispatch order in the streamed AA phase); D3Q27
+  // dispatch order (the orders measured within 1% of each other)
   const bool planes = ctx->p.storage == LBM_FP16_DEV;
   if (ctx->Q == 27)
     a.tilemap = 2;
   else if (!planes)
-    a.tilemap = 1;
+    a.tilemap = ctx->aa() ? 0 : 1;
   else
     a.tilemap = ctx->lay() == LAY_AA_N ? 2 : 0;
-  a.row_blocks = (ctx->p.nx + 255) / 256;
+  a.row_blocks = 2 * ((ctx->p.nx + 255) / 256);
   for (int k = 0; k < 27; k++) {
     a.sf[k] = ctx->sfc[k];
     a.sh[k] = ctx->shc[k];

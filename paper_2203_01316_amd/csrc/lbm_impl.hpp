@@ -459,10 +459,10 @@ __device__ __forceinline__ void solid_node(const KArgs &a, int64_t m) {
 //    streams through one contiguous eighth of the lattice, and the cache lines
 //    that neighbouring tiles of a row share through the +-1 pull shifts stay in
 //    one L2 (wide 2-D rows span several blocks);
-//  - rows per XCD: the blocks of one x-row stay on one XCD and consecutive rows
-//    go to consecutive XCDs, so all XCDs work on nearby memory (3-D, where a
-//    row is about one block and the slab order spreads the XCDs over distant
-//    DRAM pages).
+//  - chunks per XCD: runs of G consecutive blocks (G = row_blocks, a whole
+//    number of x-rows) stay on one XCD and consecutive chunks go to
+//    consecutive XCDs, so all XCDs work on nearby memory while the cache
+//    lines shared along a row stay in one L2.
 // Tail blocks that do not fill a whole round keep their own index.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {

@@ -102,9 +102,9 @@ struct KArgs {
   uint32_t div_nx, div_ny; // division by nx and ny (multiplier and shift, see
   int32_t sh_nx, sh_ny;    // div_magic in lbm_impl.hpp)
   int32_t with_uvel;       // advection velocity from the field (else u0)
-  int32_t tilemap;         // block -> tile order: 0 one slab per XCD, 1 rows per XCD,
+  int32_t tilemap;         // block -> tile order: 0 one slab per XCD, 1 chunks per XCD,
                            // 2 dispatch order
-  int32_t row_blocks;      // blocks per x-row (tilemap 1)
+  int32_t row_blocks;      // consecutive blocks per XCD chunk (tilemap 1)
   double sf[27];           // rates of f, chimera order
   double sh[27];           // rates of h, chimera order
   float sf32[27];          // the same rates rounded for FP32 arithmetic
