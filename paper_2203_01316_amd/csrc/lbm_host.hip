@@ -514,10 +514,11 @@ static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   // block orders measured best on MI355X: D2Q9 tiles one slab per XCD in
   // place (AA), chunks of two x-rows per XCD with two arrays (AB); D2Q9 FP16
   // planes one slab per XCD (dispatch order in the streamed AA phase); D3Q27
-  // dispatch order (the orders measured within 1% of each other)
+  // tiles dispatch order (the orders measured within 1% of each other);
+  // D3Q27 FP16 planes chunks of two x-rows per XCD
   const bool planes = ctx->p.storage == LBM_FP16_DEV;
   if (ctx->Q == 27)
-    a.tilemap = 2;
+    a.tilemap = planes ? 1 : 2;
   else if (!planes)
     a.tilemap = ctx->aa() ? 0 : 1;
   else
