@@ -956,20 +956,21 @@ static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b -
 
 // Residency cap of a step kernel.  The step kernels use no LDS; an unused
 // dynamic LDS request caps the blocks of 256 threads resident on one CU (160
-// KB of LDS) at `blocks`.  On MI355X the FP32 two-array steps stream faster
-// under a cap than at the residency their register count allows.  At 256^3
-// the D3Q27 central-moment step takes 1178 us at 2 blocks per CU against 1235
-// uncapped, the order-limited cumulant step 1214 at 3 against 1259; at 2048^2
-// the D2Q9 step takes 97.2 us at 3 against 100.9.  The AA layout, FP16
-// storage and the full cumulant transform measured no gain or a loss.
-// 0 = no cap.
+// KB of LDS) at `blocks`.  On MI355X the FP32 steps of D3Q27 and the D2Q9
+// two-array step stream faster under a cap than at the residency their
+// register count allows.  At 256^3 the D3Q27 central-moment step takes 1178
+// us at 2 blocks per CU against 1235 uncapped (AA: 1266 against 1369), the
+// order-limited cumulant step 1214 at 3 against 1259 (AA: 1308 at 2 against
+// 1452); at 2048^2 the D2Q9 two-array step takes 97.2 us at 3 against 100.9.
+// The D2Q9 AA layout, FP16 storage and the full cumulant transform measured
+// no gain or a loss.  0 = no cap.
 constexpr size_t lds_for_blocks(int blocks) { return (size_t)(160 * 1024) / (blocks + 1) + 1024; }
 
 template <int Q, int ST, int LAY, int CU>
 constexpr size_t step_lds() {
-  constexpr bool fp32_ab = (ST == ST_FP32 || ST == ST_FP32_DEV) && LAY == LAY_AB && (CU == 0 || (CU & 4));
-  if constexpr (Q == 27 && fp32_ab) return lds_for_blocks(CU == 0 ? 2 : 3);
-  if constexpr (Q == 9 && fp32_ab) return lds_for_blocks(3);
+  constexpr bool fp32 = (ST == ST_FP32 || ST == ST_FP32_DEV) && (CU == 0 || (CU & 4));
+  if constexpr (Q == 27 && fp32) return lds_for_blocks(LAY == LAY_AB && CU != 0 ? 3 : 2);
+  if constexpr (Q == 9 && fp32 && LAY == LAY_AB) return lds_for_blocks(3);
   return 0;
 }
 
