@@ -141,6 +141,33 @@ def test_aa_d3q27_sphere(L, storage):
         _same(L, ab, aa, ("f", "h"), cols=(3, 15), group=0)
 
 
+@pytest.mark.parametrize("cu", [False, True])
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_aa_d3q27_several_tiles(L, storage, cu):
+    """Several population tiles with a ragged last one (19,200 nodes), sphere,
+    inlet and outlet, central-moment or cumulant kernels (the in-place steps
+    run under their residency cap)."""
+    nx, ny, nz = 40, 30, 16
+    flags, q, groups = W.sphere_box(nx, ny, nz, (17.3, 14.6, 7.8), 5.2, inlet=True)
+    n = nx * ny * nz
+    u = np.zeros((3, n))
+    u[0] = 0.02
+    u = f32(u) if storage == "fp32" else u
+    H0 = 1 + 0.1 * np.random.default_rng(63).uniform(size=n)
+
+    def make(stream):
+        g = L.LBM(27, nx, ny, nz, storage=storage, with_ns=True, nu=0.03, k=0.02, flags=flags, q=q, groups=groups,
+                  stream=stream, cumulant_f=cu, cumulant_h=cu, relax_h="1st" if cu else "trt")
+        g.init(H0, u=u, rho=np.ones(n))
+        return g
+
+    ab, aa = _both(L, make)
+    for k in (1, 4):
+        ab.step(k)
+        aa.step(k)
+        _same(L, ab, aa, ("f", "h"), cols=(3, 31), group=0)
+
+
 def test_aa_full_size_cylinder(L):
     """2048^2 coupled FP32 heated cylinder (the benchmark configuration): the
     in-place layout equals the two-array one bit for bit after 1 and 3 steps."""
