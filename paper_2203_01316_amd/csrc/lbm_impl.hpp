@@ -335,15 +335,16 @@ __device__ __forceinline__ void post_addr(const KArgs &a, Node c, int64_t m, int
   }
 }
 
-// Access order of a bulk node.  D3Q27 central-moment steps pull all of f and
-// then all of h, and store, each in address order within a tile: f's
-// collision then waits only for f's loads while h's are still in flight.  On
-// MI355X this measured 1.7% faster at 256^3 (FP32 and FP16-dev); the D2Q9 and
-// cumulant steps keep direction order with f and h interleaved, which
-// measured as fast or faster for them.
+// Access order of a bulk node.  D3Q27 central-moment and order-limited
+// cumulant steps pull all of f and then all of h, and store, each in address
+// order within a tile: f's collision then waits only for f's loads while h's
+// are still in flight.  On MI355X this measured 1.7% faster at 256^3 for
+// central moments (FP32 and FP16-dev) and 2.3% for the cumulants (with the
+// residency cap); the D2Q9 and full cumulant steps keep direction order with
+// f and h interleaved, which measured as fast or faster for them.
 template <int Q, int CU>
 __device__ __forceinline__ constexpr bool split_order() {
-  return Lat<Q>::D == 3 && CU == 0;
+  return Lat<Q>::D == 3 && (CU == 0 || (CU & 4));
 }
 
 // ---------------------------------------------------------------------------
@@ -960,16 +961,16 @@ static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b -
 // two-array step stream faster under a cap than at the residency their
 // register count allows.  At 256^3 the D3Q27 central-moment step takes 1178
 // us at 2 blocks per CU against 1235 uncapped (AA: 1266 against 1369), the
-// order-limited cumulant step 1214 at 3 against 1259 (AA: 1308 at 2 against
-// 1452); at 2048^2 the D2Q9 two-array step takes 97.2 us at 3 against 100.9.
-// The D2Q9 AA layout, FP16 storage and the full cumulant transform measured
-// no gain or a loss.  0 = no cap.
+// order-limited cumulant step 1192 at 2 against 1218 at 3 and 1244 at 4 (AA:
+// 1273 against 1326 at 3); at 2048^2 the D2Q9 two-array step takes 97.2 us
+// at 3 against 100.9.  The D2Q9 AA layout, FP16 storage and the full
+// cumulant transform measured no gain or a loss.  0 = no cap.
 constexpr size_t lds_for_blocks(int blocks) { return (size_t)(160 * 1024) / (blocks + 1) + 1024; }
 
 template <int Q, int ST, int LAY, int CU>
 constexpr size_t step_lds() {
   constexpr bool fp32 = (ST == ST_FP32 || ST == ST_FP32_DEV) && (CU == 0 || (CU & 4));
-  if constexpr (Q == 27 && fp32) return lds_for_blocks(LAY == LAY_AB && CU != 0 ? 3 : 2);
+  if constexpr (Q == 27 && fp32) return lds_for_blocks(2);
   if constexpr (Q == 9 && fp32 && LAY == LAY_AB) return lds_for_blocks(3);
   return 0;
 }
