@@ -335,16 +335,18 @@ __device__ __forceinline__ void post_addr(const KArgs &a, Node c, int64_t m, int
   }
 }
 
-// Access order of a bulk node.  D3Q27 central-moment and order-limited
-// cumulant steps pull all of f and then all of h, and store, each in address
-// order within a tile: f's collision then waits only for f's loads while h's
-// are still in flight.  On MI355X this measured 1.7% faster at 256^3 for
-// central moments (FP32 and FP16-dev) and 2.3% for the cumulants (with the
-// residency cap); the D2Q9 and full cumulant steps keep direction order with
-// f and h interleaved, which measured as fast or faster for them.
-template <int Q, int CU>
+// Access order of a bulk node.  The D3Q27 steps and the D2Q9 in-place steps
+// with central moments or order-limited cumulants pull all of f and then all
+// of h, and store, each in address order within a tile: f's collision then
+// waits only for f's loads while h's are still in flight.  On MI355X this
+// measured faster at 256^3 (central moments 1.7%, FP32 and FP16-dev;
+// cumulants 2.3% with the residency cap) and for the 2048^2 D2Q9 AA step
+// (central moments 0.5%, cumulants 1.8%).  The D2Q9 two-array and the full
+// cumulant steps keep direction order with f and h interleaved, which
+// measured faster for them.
+template <int Q, int LAY, int CU>
 __device__ __forceinline__ constexpr bool split_order() {
-  return Lat<Q>::D == 3 && (CU == 0 || (CU & 4));
+  return (Lat<Q>::D == 3 || LAY != LAY_AB) && (CU == 0 || (CU & 4));
 }
 
 // ---------------------------------------------------------------------------
@@ -380,7 +382,7 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
         collide<D, R>(g, rates<R>(a, true), ux, uy, uz, R(0));
 #pragma unroll
       for (int k = 0; k < Q; k++) {
-        const int i = split_order<Q, CU>() ? dir_at_pos<Q>(k) : k;
+        const int i = split_order<Q, LAY, CU>() ? dir_at_pos<Q>(k) : k;
         int sl;
         int64_t nd;
         store_addr<Q, LAY>(a, c, m, i, sl, nd);
@@ -398,7 +400,7 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
       collide<D, R>(g, rates<R>(a, false), ux, uy, uz, src);
 #pragma unroll
     for (int k = 0; k < Q; k++) {
-      const int i = split_order<Q, CU>() ? dir_at_pos<Q>(k) : k;
+      const int i = split_order<Q, LAY, CU>() ? dir_at_pos<Q>(k) : k;
       int sl;
       int64_t nd;
       store_addr<Q, LAY>(a, c, m, i, sl, nd);
@@ -525,7 +527,7 @@ __device__ __forceinline__ void bulk_node(const KArgs &a, int64_t m) {
   if constexpr (GEOM) cl = a.cls[m];
   const Node c = coords<Q>(a, m);
   R f[Q], h[Q];
-  if constexpr (split_order<Q, CU>()) {
+  if constexpr (split_order<Q, LAY, CU>()) {
     if constexpr (NS) {
 #pragma unroll
       for (int k = 0; k < Q; k++) {
