@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -29,12 +30,21 @@ METRIC = "MLUPS + % HBM roofline (fwd CM stream-collide); adjoint/forward step-t
 
 
 def source_digest() -> str:
+    """Digest of the kernel sources and build script with comments and blank
+    lines removed, so that it changes with the code only."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2203_01316_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         if name.endswith((".hip", ".hpp")) or name == "build.py":
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(fh.read())
+            with open(os.path.join(csrc, name), encoding="utf-8") as fh:
+                text = fh.read()
+            if name.endswith((".hip", ".hpp")):
+                text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+                text = re.sub(r"//[^\n]*", "", text)
+            else:
+                text = re.sub(r"#[^\n]*", "", text)
+            lines = [ln.rstrip() for ln in text.splitlines() if ln.strip()]
+            h.update(name.encode() + b"\0" + "\n".join(lines).encode())
     return h.hexdigest()[:16]
 
 

@@ -94,7 +94,8 @@ __device__ __forceinline__ constexpr int dir_at_pos(int k) {
 // slot_offset(slot) + node_offset(m): the first is uniform over a wavefront
 // (it folds into the scalar base address), the second is shared by the slots
 // pulled from one node.  Node indices are below 2^31 (the host rejects larger
-// lattices), and (m / T) x (slots per tile) stays below 2^32 for every tile.
+// lattices), so (m / T) x (slots per tile) < 2^31 / 128 x 54 < 2^32 for every
+// tile (T >= 128 nodes, at most 54 slots).
 template <int Q, class S>
 __device__ __forceinline__ int64_t slot_offset(int slot, int64_t ps) {
   if constexpr (sizeof(S) == 2)
@@ -140,8 +141,9 @@ __device__ __forceinline__ int64_t pop_index(int slot, int64_t ps, int64_t m) {
 }
 
 // Load / store population i (stored in slot `slot`) of node m; ps is the
-// slots per tile (FP64/FP32) or the plane stride (FP16) of the layout.  The deviation storages keep g_i - w_i g_ref;
-// w_i = w_opp(i), so a swapped slot needs no other weight.
+// slots per tile (FP64/FP32) or the plane stride (FP16) of the layout.  The
+// deviation storages keep g_i - w_i g_ref; w_i = w_opp(i), so a swapped slot
+// needs no other weight.
 template <int Q, int ST, int NL = 0>
 __device__ __forceinline__ typename StT<ST>::R ldp(const void *base, int slot, int64_t ps, int64_t m,
                                                    typename StT<ST>::R ref) {
