@@ -131,7 +131,10 @@ typedef struct {
                         * paper's Cumulants-1st, LBM_CM_NS for f relaxes the
                         * second-order cumulants at s_nu).  The cumulant
                         * transform normalises by the zeroth moment, which must
-                        * not vanish. */
+                        * not vanish.  With those two presets every rate above
+                        * order 2 (f) or order 1 (h) is 1, and the library
+                        * runs a shorter transform that gives the same result
+                        * to rounding; other rates run the full one. */
   double nu;        /* kinematic viscosity (lattice units), f lattice */
   double k;         /* conductivity / diffusivity (lattice units), h lattice */
   double rho_ref;   /* deviation reference of f (the *_DEV storages) */
