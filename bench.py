@@ -252,8 +252,8 @@ def main():
     ap.add_argument("--extra-scale", type=float, default=1.0, help="scale the step counts of those legs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: only one GPU is supported in this build (got --gpus {args.gpus}); the kernel "
-              "shards by slabs, but no multi-GPU path is built", file=sys.stderr)
+        print(f"bench.py: one GPU only (got --gpus {args.gpus}); the step would shard by slabs, "
+              "but the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
