@@ -260,19 +260,22 @@ lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32
 
 /* ---- discrete adjoint ----------------------------------------------------
  * Reverse mode of the advection-diffusion step with a source Q (App. D) for
- * contexts with with_ns = 0, no geometry (fully periodic) and the
- * central-moment collision of h; other contexts return LBM_EUNSUPPORTED.  Not in the paper: the reverse step is the exact
- * transpose of the forward step.  That step is affine in (state, Q) for a
- * prescribed velocity, so the reverse step needs no forward state.
+ * contexts with with_ns = 0 and the central-moment collision of h, periodic
+ * or with geometry: ABB/IABB walls (Eq. IABB) and EQ nodes; outlet nodes and
+ * other contexts return LBM_EUNSUPPORTED.  Not in the paper: the reverse
+ * step is the exact transpose of the forward step.  That step is affine in
+ * (state, Q) for a prescribed velocity, so the reverse step needs no forward
+ * state.  Solid nodes carry no state: their lambda is ignored on input and
+ * zero on output.
  * lambda: adjoint of the canonical (pre-collision) state, device [Q][n] in
  * the arithmetic type (double for LBM_FP64, float otherwise); dJdQ: device
  * FP64 [n], an accumulator over all reverse steps. */
 
-/* Objective J = 1/2 sum_x (H(x) - H_target(x))^2 of the canonical state at the
- * current time (H = sum h + Q/2).  Writes lambda = dJ/d(state) (every
- * direction H - H_target), sets dJdQ = (H - H_target)/2 (the direct
- * dependence through Q/2) and returns J (synchronises).  H_target: device
- * FP64 [n]. */
+/* Objective J = 1/2 sum_x (H(x) - H_target(x))^2 over the non-solid nodes of
+ * the canonical state at the current time (H = sum h + Q/2).  Writes lambda =
+ * dJ/d(state) (every direction H - H_target, zero at solid nodes), sets
+ * dJdQ = (H - H_target)/2 (the direct dependence through Q/2) and returns J
+ * (synchronises).  H_target: device FP64 [n]. */
 lbm_status lbm_objective(lbm_ctx *ctx, const double *H_target_dev, void *lambda_dev, void *dJdQ_dev,
                          double *J);
 

@@ -330,22 +330,74 @@ class Sim:
         assert lib().ora_adjoint_step(C.byref(self.cfg), _p(lam_next), _p(out), _p(dJdQ)) == 0
         return out
 
+    def adjoint_step_dense(self, lam_next, dJdQ=None):
+        """The adjoint step as the plain transpose of the one-step map from the
+        canonical state at t to that at t + 1 (collision, then streaming with
+        the wall rules, EQ nodes and the source).  For a prescribed velocity
+        that map is affine in the state and in the source, so each column is
+        the forward step of a unit vector minus the step of zero.  Small
+        lattices only; the advection-diffusion lattice only."""
+        assert not self.with_ns
+        Q, N = self.Q, self.N
+        lam = np.array(lam_next, dtype=np.float64).reshape(Q, N)
+        solid = self._solid()
+        lam[:, solid] = 0.0  # solid nodes carry no state
+        src0 = None if self.src is None else self.src.copy()
+        saved = (self.post_f, self.post_h, self.t)
+        zero = np.zeros((Q, N))
+
+        def F(h, src):
+            self.set_source(src)
+            _, hs = self.collide(zero, h)
+            self.post_h = hs
+            return self.pre()[1]
+
+        try:
+            base = F(zero, src0)
+            out = np.zeros(Q * N)
+            e = np.zeros(Q * N)
+            for k in range(Q * N):
+                e[k] = 1.0
+                out[k] = float(((F(e.reshape(Q, N), src0) - base) * lam).sum())
+                e[k] = 0.0
+            if dJdQ is not None:
+                b0 = F(zero, np.zeros(N))
+                unit = np.zeros(N)
+                for m in range(N):
+                    unit[m] = 1.0
+                    dJdQ[m] += float(((F(zero, unit) - b0) * lam).sum())
+                    unit[m] = 0.0
+        finally:
+            self.set_source(src0)
+            self.post_f, self.post_h, self.t = saved
+        out = out.reshape(Q, N)
+        out[:, solid] = 0.0
+        return out
+
+    def _solid(self):
+        if self.flags is None:
+            return np.zeros(self.N, dtype=bool)
+        return (self.flags & 15) == 1
+
     def objective(self, H_target):
-        """J = 1/2 sum (H - H*)^2 of the canonical state, dJ/dpre (all
-        directions equal H - H*) and the direct part of dJ/dQ (Q enters H as Q/2)."""
+        """J = 1/2 sum over the non-solid nodes of (H - H*)^2 of the canonical
+        state, dJ/dpre (all directions equal H - H*) and the direct part of
+        dJ/dQ (Q enters H as Q/2)."""
         _, _, H = self.macroscopic()
         r = H - np.asarray(H_target, dtype=np.float64).reshape(-1)
+        r[self._solid()] = 0.0
         lam = np.repeat(r[None, :], self.Q, axis=0)
         return 0.5 * float((r * r).sum()), lam, 0.5 * r
 
-    def gradient_source(self, H_target, steps):
+    def gradient_source(self, H_target, steps, dense=False):
         """J and dJ/dQ after `steps` steps from the current post state (which
-        must be the initial one): forward, objective, then reverse steps."""
+        must be the initial one): forward, objective, then reverse steps
+        (dense: with adjoint_step_dense, which also covers geometry)."""
         self.step(steps)
         J, lam, dJdQ = self.objective(H_target)
         dJdQ = np.ascontiguousarray(dJdQ)
         for _ in range(steps):
-            lam = self.adjoint_step(lam, dJdQ)
+            lam = self.adjoint_step_dense(lam, dJdQ) if dense else self.adjoint_step(lam, dJdQ)
         return J, dJdQ
 
     def section_flux(self, X, h=None):

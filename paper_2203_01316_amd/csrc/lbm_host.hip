@@ -416,6 +416,7 @@ struct lbm_ctx {
   const void *src;
   double sf[27], sh[27];  // moment order of the header
   double sfc[27], shc[27];  // chimera order
+  bool has_outlet = false;  // the geometry has outlet nodes (no adjoint)
   int cu_kernel;            // collision selector of the step kernels (cumulant bits,
                             // plus 4 when the order-limited cumulant transform applies)
   int64_t t;
@@ -747,6 +748,10 @@ lbm_status lbm_set_geometry(lbm_ctx *ctx, const uint16_t *flags, const double *q
   ctx->geom = G.any;
   ctx->nlinks = nl;
   ctx->nspecial = ns;
+  ctx->has_outlet = false;
+  if (flags)
+    for (int64_t m = 0; m < ctx->n && !ctx->has_outlet; m++)
+      ctx->has_outlet = (flags[m] & 15) == LBM_NODE_OUTLET;
   ctx->host_links = std::move(G.links);
   if (ctx->initialized) return rebuild_side(ctx);
   return LBM_OK;
@@ -950,9 +955,9 @@ lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32
 }
 
 static lbm_status need_adjoint(lbm_ctx *ctx) {
-  if (ctx->p.with_ns || ctx->geom || (ctx->p.cumulant & 1)) {
-    set_err(&ctx->err, "the adjoint is built for advection-only contexts without geometry (periodic) and with "
-            "the central-moment collision");
+  if (ctx->p.with_ns || ctx->has_outlet || (ctx->p.cumulant & 1)) {
+    set_err(&ctx->err, "the adjoint is built for advection-only contexts with the central-moment collision, "
+            "periodic or with walls and EQ nodes (no outlet nodes)");
     return LBM_EUNSUPPORTED;
   }
   if (ctx->p.u_mode == 1 && !ctx->uvel) {
@@ -977,7 +982,7 @@ lbm_status lbm_objective(lbm_ctx *ctx, const double *H_target_dev, void *lambda_
   KArgs a = make_args(ctx, ctx->cur);
   a.out2 = H;
   if (lbm_status st = run_pass(ctx, MODE_MACRO, a)) return st;
-  HIP_TRY(ctx, launch_seed(ctx->Q, ctx->p.storage == LBM_FP64, H, H_target_dev, ctx->n, lambda_dev, dJdQ_dev, sq,
+  HIP_TRY(ctx, launch_seed(ctx->Q, ctx->p.storage == LBM_FP64, H, H_target_dev, a.cls, ctx->n, lambda_dev, dJdQ_dev, sq,
                            ctx->stream), "seed kernel launch");
   HIP_TRY(ctx, launch_reduce(nullptr, sq, nullptr, ctx->n, ctx->p.nx, ctx->p.ny, ctx->p.nz, nullptr, 0, nullptr,
                              nullptr, 0, 0, reinterpret_cast<double *>(ctx->ws + ctx->L.off_part), kPartials, res,

@@ -873,7 +873,7 @@ __global__ void __launch_bounds__(256) k_convert(const KArgs a, const void *from
 }
 
 // ---------------------------------------------------------------------------
-// Discrete adjoint of the advection-diffusion step (no geometry): node y
+// Discrete adjoint of the periodic advection-diffusion step: node y
 // gathers lam_next_i(y + e_i) (transpose of the pull), applies the transposed
 // collision of node y and writes lam_prev(y); dJdQ(y) += b^T lam.
 // ---------------------------------------------------------------------------
@@ -897,14 +897,96 @@ __global__ void __launch_bounds__(256) k_adjoint(const KArgs a, const R *lam_nex
   if (dJdQ) dJdQ[m] += double(dq);
 }
 
-// Objective J = 1/2 sum (H - H*)^2: seeds lam = dJ/dpre (every direction
+// Discrete adjoint of the advection-diffusion step with geometry (walls
+// ABB/IABB of Eq. IABB, EQ nodes; no outlets), in three passes over lam_prev:
+//  1. mu_i(y) = lam_next_i(y + e_i) where node y + e_i pulls h*_i(y) (not
+//     solid, not an EQ node: those take no pulled value);
+//  2. per boundary-node record, the transpose of its wall rules, and the
+//     removal of pass-1 terms gathered from a listed EQ node;
+//  3. the transposed collision of each node in place; dJdQ(y) += b^T mu.
+// Pass 2 adds with atomics: two walls one node apart can feed one entry.
+template <int Q, class R>
+__global__ void __launch_bounds__(256) k_adj_gather(const KArgs a, const R *lam_next, R *mu) {
+  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (m >= a.n) return;
+  const bool solid = a.cls[m] == CLS_SOLID;
+  const Node c = coords<Q>(a, m);
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    const int64_t d = shifted<Q>(a, c, i, +1);
+    const uint8_t cd = a.cls[d];
+    const bool pulled = !solid && cd != CLS_SOLID && cd < CLS_EQ;
+    mu[(int64_t)i * a.n + m] = pulled ? lam_next[(int64_t)i * a.n + d] : R(0);
+  }
+}
+
+template <int Q, class R>
+__global__ void __launch_bounds__(64) k_adj_walls(const KArgs a, const R *lam_next, R *mu) {
+  const int64_t r = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (r >= a.nspecial) return;
+  const DevSpecial sp = a.special[r];
+  const int64_t m = sp.node;
+  const Node c = coords<Q>(a, m);
+  if (sp.type == NODE_EQ) {
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      const int64_t y = shifted<Q>(a, c, i, -1);
+      if (a.cls[y] == CLS_SOLID) continue;
+      atomicAdd(mu + (int64_t)i * a.n + y, -lam_next[(int64_t)i * a.n + m]);
+    }
+    return;
+  }
+  const DevWall<R> *walls = static_cast<const DevWall<R> *>(a.walls) + sp.lb;
+  int l = 0;
+#pragma unroll
+  for (int i = 1; i < Q; i++) {
+    if (!((sp.mask >> i) & 1u)) continue;
+    const DevWall<R> w = walls[l++];
+    const int o = Lat<Q>::opp(i);
+    // forward: h_o(x_b) from h*_i(x_b), h*_o(x_b) and the pulled h*_i(x_b - e_i)
+    const R lo = lam_next[(int64_t)o * a.n + m];
+    if (!(w.interp & 2)) {
+      atomicAdd(mu + (int64_t)i * a.n + m, -lo);
+    } else if (w.q <= R(0.5)) {
+      atomicAdd(mu + (int64_t)i * a.n + m, -R(2) * w.q * lo);
+      atomicAdd(mu + (int64_t)i * a.n + shifted<Q>(a, c, i, -1), -(R(1) - R(2) * w.q) * lo);
+    } else {
+      atomicAdd(mu + (int64_t)i * a.n + m, -lo / (R(2) * w.q));
+      atomicAdd(mu + (int64_t)o * a.n + m, (R(2) * w.q - R(1)) * lo / (R(2) * w.q));
+    }
+  }
+}
+
+template <int Q, class R>
+__global__ void __launch_bounds__(256) k_adj_collide(const KArgs a, R *lam, double *dJdQ) {
+  constexpr int D = Lat<Q>::D;
+  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (m >= a.n) return;
+  if (a.cls[m] == CLS_SOLID) {
+#pragma unroll
+    for (int i = 0; i < Q; i++) lam[(int64_t)i * a.n + m] = R(0);
+    return;
+  }
+  R g[Q];
+#pragma unroll
+  for (int i = 0; i < Q; i++) g[Lat<Q>::slot(i)] = lam[(int64_t)i * a.n + m];
+  R ux, uy, uz;
+  prescribed_u<Q, R>(a, m, ux, uy, uz);
+  const R dq = collide_adjoint<D, R>(g, rates<R>(a, false), ux, uy, uz);
+#pragma unroll
+  for (int i = 0; i < Q; i++) lam[(int64_t)i * a.n + m] = g[Lat<Q>::slot(i)];
+  if (dJdQ) dJdQ[m] += double(dq);
+}
+
+// Objective J = 1/2 sum (H - H*)^2 over the non-solid nodes (solid nodes
+// carry no state): seeds lam = dJ/dpre (every direction
 // H - H*), sets dJdQ = (H - H*)/2 (Q enters H as Q/2), leaves (H - H*)^2 in sq.
 template <int Q, class R>
-__global__ void __launch_bounds__(256) k_seed(const double *H, const double *Ht, int64_t n, R *lam, double *dJdQ,
-                                              double *sq) {
+__global__ void __launch_bounds__(256) k_seed(const double *H, const double *Ht, const uint8_t *cls, int64_t n, R *lam,
+                                              double *dJdQ, double *sq) {
   const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (m >= n) return;
-  const double d = H[m] - Ht[m];
+  const double d = (cls && cls[m] == CLS_SOLID) ? 0.0 : H[m] - Ht[m];
 #pragma unroll
   for (int i = 0; i < Q; i++) lam[(int64_t)i * n + m] = R(d);
   dJdQ[m] = 0.5 * d;
@@ -1035,8 +1117,20 @@ static hipError_t convert_t(bool to_storage, const KArgs &a, const void *from, v
 
 template <int Q, class R>
 static hipError_t adjoint_t(const KArgs &a, const void *ln, void *lp, void *dq, hipStream_t s) {
-  k_adjoint<Q, R><<<blocks_for(a.n, 256), 256, 0, s>>>(a, static_cast<const R *>(ln), static_cast<R *>(lp),
-                                                         static_cast<double *>(dq));
+  const R *lam_next = static_cast<const R *>(ln);
+  R *lam_prev = static_cast<R *>(lp);
+  double *dJdQ = static_cast<double *>(dq);
+  if (!a.cls) {
+    k_adjoint<Q, R><<<blocks_for(a.n, 256), 256, 0, s>>>(a, lam_next, lam_prev, dJdQ);
+    return hipGetLastError();
+  }
+  k_adj_gather<Q, R><<<blocks_for(a.n, 256), 256, 0, s>>>(a, lam_next, lam_prev);
+  if (hipError_t e = hipGetLastError()) return e;
+  if (a.nspecial > 0) {
+    k_adj_walls<Q, R><<<blocks_for(a.nspecial, 64), 64, 0, s>>>(a, lam_next, lam_prev);
+    if (hipError_t e = hipGetLastError()) return e;
+  }
+  k_adj_collide<Q, R><<<blocks_for(a.n, 256), 256, 0, s>>>(a, lam_prev, dJdQ);
   return hipGetLastError();
 }
 
@@ -1089,10 +1183,11 @@ struct Launch {
   static hipError_t adjoint(const KArgs &a, const void *ln, void *lp, void *dq, hipStream_t s) {
     return adjoint_t<Q, typename StT<ST>::R>(a, ln, lp, dq, s);
   }
-  static hipError_t seed(const double *H, const double *Ht, int64_t n, void *lam, void *dq, double *sq,
-                         hipStream_t s) {
+  static hipError_t seed(const double *H, const double *Ht, const uint8_t *cls, int64_t n, void *lam, void *dq,
+                         double *sq, hipStream_t s) {
     using R = typename StT<ST>::R;
-    k_seed<Q, R><<<blocks_for(n, 256), 256, 0, s>>>(H, Ht, n, static_cast<R *>(lam), static_cast<double *>(dq), sq);
+    k_seed<Q, R><<<blocks_for(n, 256), 256, 0, s>>>(H, Ht, cls, n, static_cast<R *>(lam), static_cast<double *>(dq),
+                                                      sq);
     return hipGetLastError();
   }
 };
@@ -1120,9 +1215,9 @@ struct Launch {
   hipError_t NAME##_adjoint(const KArgs &a, const void *ln, void *lp, void *dq, hipStream_t s) {              \
     return Launch<Q, ST>::adjoint(a, ln, lp, dq, s);                                                          \
   }                                                                                                           \
-  hipError_t NAME##_seed(const double *H, const double *Ht, int64_t n, void *lam, void *dq, double *sq,       \
-                         hipStream_t s) {                                                                     \
-    return Launch<Q, ST>::seed(H, Ht, n, lam, dq, sq, s);                                                     \
+  hipError_t NAME##_seed(const double *H, const double *Ht, const uint8_t *cls, int64_t n, void *lam, void *dq, \
+                         double *sq, hipStream_t s) {                                                         \
+    return Launch<Q, ST>::seed(H, Ht, cls, n, lam, dq, sq, s);                                                \
   }
 
 }  // namespace lbm

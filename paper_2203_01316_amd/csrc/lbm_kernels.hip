@@ -13,7 +13,8 @@ namespace lbm {
   hipError_t NAME##_init(bool, int, const InitArgs &, hipStream_t);                                   \
   hipError_t NAME##_convert(int, bool, const KArgs &, const void *, void *, double, hipStream_t);      \
   hipError_t NAME##_adjoint(const KArgs &, const void *, void *, void *, hipStream_t);                \
-  hipError_t NAME##_seed(const double *, const double *, int64_t, void *, void *, double *, hipStream_t);
+  hipError_t NAME##_seed(const double *, const double *, const uint8_t *, int64_t, void *, void *, double *,  \
+                         hipStream_t);
 LBM_DECLARE(q9_fp64)
 LBM_DECLARE(q9_fp32)
 LBM_DECLARE(q9_fp32dev)
@@ -68,9 +69,9 @@ hipError_t launch_adjoint(int Q, bool fp64, const KArgs &a, const void *lam_next
                           hipStream_t s) {
   LBM_SELECT(Q, fp64 ? ST_FP64 : ST_FP32, adjoint, a, lam_next, lam_prev, dJdQ, s);
 }
-hipError_t launch_seed(int Q, bool fp64, const double *H, const double *Ht, int64_t n, void *lam, void *dJdQ,
-                       double *sq, hipStream_t s) {
-  LBM_SELECT(Q, fp64 ? ST_FP64 : ST_FP32, seed, H, Ht, n, lam, dJdQ, sq, s);
+hipError_t launch_seed(int Q, bool fp64, const double *H, const double *Ht, const uint8_t *cls, int64_t n, void *lam,
+                       void *dJdQ, double *sq, hipStream_t s) {
+  LBM_SELECT(Q, fp64 ? ST_FP64 : ST_FP32, seed, H, Ht, cls, n, lam, dJdQ, sq, s);
 }
 
 // ---------------------------------------------------------------------------

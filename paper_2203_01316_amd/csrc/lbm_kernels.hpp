@@ -156,7 +156,8 @@ hipError_t launch_reduce(const double *rho, const double *H, const double *qx, i
                          int npartials, double *out, hipStream_t s);
 hipError_t launch_adjoint(int Q, bool fp64, const KArgs &a, const void *lam_next, void *lam_prev, void *dJdQ,
                           hipStream_t s);
-hipError_t launch_seed(int Q, bool fp64, const double *H, const double *Ht, int64_t n, void *lam, void *dJdQ,
-                       double *sq, hipStream_t s);
+// cls: node classes or null; solid nodes are left out of the objective.
+hipError_t launch_seed(int Q, bool fp64, const double *H, const double *Ht, const uint8_t *cls, int64_t n, void *lam,
+                       void *dJdQ, double *sq, hipStream_t s);
 
 }  // namespace lbm

@@ -178,6 +178,22 @@ def channel(nx: int = 1024, ny: int = 256, cx: float = 256, cy: float = 128, r: 
     return flags, q, groups, u
 
 
+def walled_box(nx: int = 24, ny: int = 14, cx: float = 8.3, cy: float = 6.6, r: float = 2.7,
+               u_max: float = 0.04):
+    """The channel above made periodic in x (no inlet or outlet column): walls at
+    y = 0 and y = ny-1 (group 0, ABB, H = 0.5), a disc (group 2, IABB, H = 2),
+    a 2 x 2 patch of EQ nodes (group 1, H = 1.5) at x = 0.7 nx and two EQ nodes
+    on the lower wall (they have cut links).  Returns (flags, q, groups, u)."""
+    flags, q, groups, u = channel(nx, ny, cx, cy, r, u_max, H_wall=0.5, H_in=1.5, H_cyl=2.0)
+    f2 = flags.reshape(ny, nx).copy()
+    f2[1:ny - 1, 0] = flag(FLUID, 0)
+    f2[1:ny - 1, nx - 1] = flag(FLUID, 0)
+    ex, ey = int(0.7 * nx), ny // 2
+    f2[ey:ey + 2, ex:ex + 2] = flag(EQ, 1)
+    f2[1, 3:5] = flag(EQ, 1)
+    return f2.reshape(-1), q, groups, u
+
+
 def heated_cylinder(nx: int = 2048, ny: int = 2048, r: float = 64, cx=None, cy=None,
                     u_in: float = 0.04, amp: float = 1e-3, seed: int = 0, T_in: float = 10.0,
                     T_cyl: float = 11.0):

@@ -1,6 +1,7 @@
-"""GPU discrete adjoint against the oracle's adjoint and against central finite
-differences of the GPU's own FP64 forward (the objective is quadratic in the
-source, so the central difference has no truncation error)."""
+"""GPU discrete adjoint against the oracle's adjoint (periodic, and with walls
+and EQ nodes) and against central finite differences of the GPU's own FP64
+forward (the objective is quadratic in the source, so the central difference
+has no truncation error)."""
 import numpy as np
 import pytest
 
@@ -123,12 +124,88 @@ def test_c5_gradient_vs_central_differences(L):
     assert per_node.max() < 1e-3
 
 
-def test_adjoint_rejects_geometry(L):
+def _walls(W, Q):
+    if Q == 9:
+        dims = (24, 14, 1)
+        flags, q, groups, u = W.walled_box(*dims[:2])
+    else:
+        dims = (8, 7, 6)
+        flags, q, groups = W.sphere_box(*dims, (3.6, 3.3, 2.8), 1.7)
+        u = np.zeros((3, int(np.prod(dims))))
+        u[0] = 0.03
+        u[1] = -0.01
+    return dims, flags, q, groups, u
+
+
+@pytest.mark.parametrize("Q,storage,tol", [(9, "fp64", 1e-12), (9, "fp32", 1e-5), (27, "fp64", 1e-12),
+                                           (27, "fp32", 1e-5)])
+def test_adjoint_step_with_walls_matches_oracle(L, oracle, Q, storage, tol):
+    """Walls (ABB and IABB on a disc, IABB on a sphere), EQ nodes with and
+    without cut links: one GPU adjoint step against the oracle's transpose of
+    its own forward step."""
     import torch
+    from paper_2203_01316_amd import workloads as W
+    dims, flags, q, groups, u = _walls(W, Q)
+    n = int(np.prod(dims))
+    if storage == "fp32":
+        u = f32(u)
+    g = L.LBM(Q, *dims, storage=storage, k=0.02, with_source=True, u_mode=1, flags=flags, q=q, groups=groups)
+    g.set_velocity(u)
+    g.set_source(np.zeros(n))
+    _, sh = L.relaxation_rates(g.params)
+    o = oracle.Sim(Q, *dims, s_h=sh, uvel=u, src=np.zeros(n), flags=flags, qlink=q, groups=groups)
+    rng = np.random.default_rng(52)
+    lam = rng.standard_normal((Q, n))
+    if storage == "fp32":
+        lam = f32(lam)
+    lt = torch.as_tensor(lam, dtype=g.rdtype, device=g.device)
+    out = torch.empty_like(lt)
+    dq = torch.zeros(n, dtype=torch.float64, device=g.device)
+    g.adjoint_step(lt, out, dq)
+    g.sync()
+    dq_o = np.zeros(n)
+    ref = o.adjoint_step_dense(lam, dq_o)
+    assert rel_l2(out.cpu().numpy(), ref) < tol
+    assert rel_l2(dq.cpu().numpy(), dq_o) < tol
+
+
+def test_gradient_with_walls_matches_oracle(L, oracle):
+    """J and dJ/dQ after 12 steps of the walled box (FP64) equal the oracle's."""
+    import torch
+    from paper_2203_01316_amd import workloads as W
+    from paper_2203_01316_amd.adjoint import source_objective
+    T = 12
+    dims, flags, q, groups, u = _walls(W, 9)
+    n = int(np.prod(dims))
+    rng = np.random.default_rng(53)
+    src = 0.01 * rng.standard_normal(n)
+    target = 1.0 + 0.01 * rng.standard_normal(n)
+    H0 = 1.0 + 0.1 * rng.uniform(size=n)
+    g = L.LBM(9, *dims, storage="fp64", k=0.02, with_source=True, u_mode=1, flags=flags, q=q, groups=groups)
+    g.set_velocity(u)
+    qt = torch.tensor(src, dtype=torch.float64, device=g.device, requires_grad=True)
+    J = source_objective(qt, g, H0, target, T, recompute=True)
+    J.backward()
+    _, sh = L.relaxation_rates(g.params)
+    o = oracle.Sim(9, *dims, s_h=sh, uvel=u, src=src, flags=flags, qlink=q, groups=groups)
+    o.init(H0)
+    Jo, go = o.gradient_source(target, T, dense=True)
+    assert float(J.detach()) == pytest.approx(Jo, rel=1e-12)
+    assert rel_l2(qt.grad.cpu().numpy(), go) < 1e-11
+
+
+def test_adjoint_rejects_outlets_and_flow(L):
+    """Outlet nodes and the hydrodynamic lattice have no adjoint."""
+    import torch
+    from paper_2203_01316_amd import workloads as W
     flags = np.zeros(64, np.uint16)
-    flags[10] = 1
+    flags[10] = W.flag(W.OUTLET)
     g = L.LBM(9, 8, 8, k=0.01, with_source=True, flags=flags, groups=[dict()])
     lam = torch.zeros(9, 64, dtype=torch.float32, device=g.device)
     with pytest.raises(L.LBMError) as e:
         g.adjoint_step(lam, torch.empty_like(lam))
+    assert e.value.status == L.EUNSUPPORTED
+    g2 = L.LBM(9, 8, 8, k=0.01, nu=0.02, with_ns=True)
+    with pytest.raises(L.LBMError) as e:
+        g2.adjoint_step(lam, torch.empty_like(lam))
     assert e.value.status == L.EUNSUPPORTED
