@@ -261,8 +261,8 @@ lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32
 /* ---- discrete adjoint ----------------------------------------------------
  * Reverse mode of the advection-diffusion step with a source Q (App. D) for
  * contexts with with_ns = 0 and the central-moment collision of h, periodic
- * or with geometry: ABB/IABB walls (Eq. IABB) and EQ nodes; outlet nodes and
- * other contexts return LBM_EUNSUPPORTED.  Not in the paper: the reverse
+ * or with geometry (ABB/IABB walls of Eq. IABB, EQ nodes, outlets); other
+ * contexts return LBM_EUNSUPPORTED.  Not in the paper: the reverse
  * step is the exact transpose of the forward step.  That step is affine in
  * (state, Q) for a prescribed velocity, so the reverse step needs no forward
  * state.  Solid nodes carry no state: their lambda is ignored on input and

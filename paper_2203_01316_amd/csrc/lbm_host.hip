@@ -416,7 +416,6 @@ struct lbm_ctx {
   const void *src;
   double sf[27], sh[27];  // moment order of the header
   double sfc[27], shc[27];  // chimera order
-  bool has_outlet = false;  // the geometry has outlet nodes (no adjoint)
   int cu_kernel;            // collision selector of the step kernels (cumulant bits,
                             // plus 4 when the order-limited cumulant transform applies)
   int64_t t;
@@ -748,10 +747,6 @@ lbm_status lbm_set_geometry(lbm_ctx *ctx, const uint16_t *flags, const double *q
   ctx->geom = G.any;
   ctx->nlinks = nl;
   ctx->nspecial = ns;
-  ctx->has_outlet = false;
-  if (flags)
-    for (int64_t m = 0; m < ctx->n && !ctx->has_outlet; m++)
-      ctx->has_outlet = (flags[m] & 15) == LBM_NODE_OUTLET;
   ctx->host_links = std::move(G.links);
   if (ctx->initialized) return rebuild_side(ctx);
   return LBM_OK;
@@ -955,9 +950,8 @@ lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32
 }
 
 static lbm_status need_adjoint(lbm_ctx *ctx) {
-  if (ctx->p.with_ns || ctx->has_outlet || (ctx->p.cumulant & 1)) {
-    set_err(&ctx->err, "the adjoint is built for advection-only contexts with the central-moment collision, "
-            "periodic or with walls and EQ nodes (no outlet nodes)");
+  if (ctx->p.with_ns || (ctx->p.cumulant & 1)) {
+    set_err(&ctx->err, "the adjoint is built for advection-only contexts with the central-moment collision");
     return LBM_EUNSUPPORTED;
   }
   if (ctx->p.u_mode == 1 && !ctx->uvel) {

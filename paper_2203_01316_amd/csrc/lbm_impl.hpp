@@ -898,11 +898,13 @@ __global__ void __launch_bounds__(256) k_adjoint(const KArgs a, const R *lam_nex
 }
 
 // Discrete adjoint of the advection-diffusion step with geometry (walls
-// ABB/IABB of Eq. IABB, EQ nodes; no outlets), in three passes over lam_prev:
+// ABB/IABB of Eq. IABB, EQ nodes, outlets), in three passes over lam_prev:
 //  1. mu_i(y) = lam_next_i(y + e_i) where node y + e_i pulls h*_i(y) (not
-//     solid, not an EQ node: those take no pulled value);
-//  2. per boundary-node record, the transpose of its wall rules, and the
-//     removal of pass-1 terms gathered from a listed EQ node;
+//     solid, not an EQ node, not the e_x < 0 populations of a bulk outlet),
+//     plus the copy of a bulk outlet whose upstream node y + e_i is;
+//  2. per boundary-node record, the transpose of its wall rules; for a listed
+//     EQ node or outlet, the removal of pass-1 terms that are not pulls, and
+//     for an outlet the transpose of its copy;
 //  3. the transposed collision of each node in place; dJdQ(y) += b^T mu.
 // Pass 2 adds with atomics: two walls one node apart can feed one entry.
 template <int Q, class R>
@@ -915,8 +917,34 @@ __global__ void __launch_bounds__(256) k_adj_gather(const KArgs a, const R *lam_
   for (int i = 0; i < Q; i++) {
     const int64_t d = shifted<Q>(a, c, i, +1);
     const uint8_t cd = a.cls[d];
-    const bool pulled = !solid && cd != CLS_SOLID && cd < CLS_EQ;
-    mu[(int64_t)i * a.n + m] = pulled ? lam_next[(int64_t)i * a.n + d] : R(0);
+    // a bulk outlet copies its e_x < 0 populations from node x - 1 instead
+    const bool copied = Lat<Q>::ex(i) < 0 && cd == CLS_OUTLET;
+    const bool pulled = !solid && cd != CLS_SOLID && cd < CLS_EQ && !copied;
+    R v = pulled ? lam_next[(int64_t)i * a.n + d] : R(0);
+    if (Lat<Q>::ex(i) < 0 && pulled && cd == CLS_BULK) {
+      // node d + e_x may be a bulk outlet that copies h_i(d) = h*_i(m)
+      int64_t d2 = c.X[1] + c.Y[1 + Lat<Q>::ey(i)];
+      if constexpr (Lat<Q>::D == 3) d2 += c.Z[1 + Lat<Q>::ez(i)];
+      if (a.cls[d2] == CLS_OUTLET) v += lam_next[(int64_t)i * a.n + d2];
+    }
+    mu[(int64_t)i * a.n + m] = v;
+  }
+}
+
+// Transpose of the wall rule that writes h_o(x) from h*_i(x), h*_o(x) and the
+// pulled h*_i(x - e_i) (o = opp(i)), applied to the adjoint lo of h_o(x).
+template <int Q, class R>
+__device__ __forceinline__ void adj_wall(const KArgs &a, const Node &c, int64_t m, int i, const DevWall<R> &w, R lo,
+                                         R *mu) {
+  const int o = Lat<Q>::opp(i);
+  if (!(w.interp & 2)) {
+    atomicAdd(mu + (int64_t)i * a.n + m, -lo);
+  } else if (w.q <= R(0.5)) {
+    atomicAdd(mu + (int64_t)i * a.n + m, -R(2) * w.q * lo);
+    atomicAdd(mu + (int64_t)i * a.n + shifted<Q>(a, c, i, -1), -(R(1) - R(2) * w.q) * lo);
+  } else {
+    atomicAdd(mu + (int64_t)i * a.n + m, -lo / (R(2) * w.q));
+    atomicAdd(mu + (int64_t)o * a.n + m, (R(2) * w.q - R(1)) * lo / (R(2) * w.q));
   }
 }
 
@@ -936,23 +964,36 @@ __global__ void __launch_bounds__(64) k_adj_walls(const KArgs a, const R *lam_ne
     }
     return;
   }
-  const DevWall<R> *walls = static_cast<const DevWall<R> *>(a.walls) + sp.lb;
-  int l = 0;
+  const bool outlet = sp.type == NODE_OUTLET;
+  const DevWall<R> *walls = static_cast<const DevWall<R> *>(a.walls);
+  int l = sp.lb;
 #pragma unroll
   for (int i = 1; i < Q; i++) {
     if (!((sp.mask >> i) & 1u)) continue;
     const DevWall<R> w = walls[l++];
     const int o = Lat<Q>::opp(i);
-    // forward: h_o(x_b) from h*_i(x_b), h*_o(x_b) and the pulled h*_i(x_b - e_i)
-    const R lo = lam_next[(int64_t)o * a.n + m];
-    if (!(w.interp & 2)) {
-      atomicAdd(mu + (int64_t)i * a.n + m, -lo);
-    } else if (w.q <= R(0.5)) {
-      atomicAdd(mu + (int64_t)i * a.n + m, -R(2) * w.q * lo);
-      atomicAdd(mu + (int64_t)i * a.n + shifted<Q>(a, c, i, -1), -(R(1) - R(2) * w.q) * lo);
+    // an outlet's e_x < 0 populations are copied, not taken from its walls
+    if (outlet && Lat<Q>::ex(o) < 0) continue;
+    adj_wall<Q, R>(a, c, m, i, w, lam_next[(int64_t)o * a.n + m], mu);
+  }
+  if (!outlet) return;
+  // h_j(x_o) = h_j(u) for e_x < 0, u = x_o - 1: the gather took lam_j(x_o) as
+  // a pull, which it is not; it goes to what h_j(u) came from instead
+  const int64_t u = c.x == 0 ? m + a.nx - 1 : m - 1;
+  const Node cu = coords<Q>(a, u);
+#pragma unroll
+  for (int j = 0; j < Q; j++) {
+    if (Lat<Q>::ex(j) >= 0) continue;
+    const R lx = lam_next[(int64_t)j * a.n + m];
+    const int64_t y = shifted<Q>(a, c, j, -1);
+    if (a.cls[y] != CLS_SOLID) atomicAdd(mu + (int64_t)j * a.n + y, -lx);
+    const int i = Lat<Q>::opp(j);
+    if ((sp.umask >> i) & 1u) {
+      // h_j(u) is the wall rule of u's cut link i
+      const DevWall<R> w = walls[sp.ub + __popc(sp.umask & ((1u << i) - 1u))];
+      adj_wall<Q, R>(a, cu, u, i, w, lx, mu);
     } else {
-      atomicAdd(mu + (int64_t)i * a.n + m, -lo / (R(2) * w.q));
-      atomicAdd(mu + (int64_t)o * a.n + m, (R(2) * w.q - R(1)) * lo / (R(2) * w.q));
+      atomicAdd(mu + (int64_t)j * a.n + shifted<Q>(a, cu, j, -1), lx);
     }
   }
 }

@@ -97,12 +97,17 @@ def test_dense_adjoint_equals_periodic_adjoint(oracle, Q, L):
     assert np.abs(d1 - d2).max() < 1e-12 * np.abs(d1).max()
 
 
-def test_dense_adjoint_with_walls_vs_central_differences(oracle):
-    """Walls (ABB, IABB on a disc), EQ nodes with and without cut links and a
-    prescribed Poiseuille velocity: the gradient of J from the probed adjoint
-    equals central differences of the forward oracle (J is quadratic in Q)."""
+@pytest.mark.parametrize("case", ["walled", "channel"])
+def test_dense_adjoint_with_walls_vs_central_differences(oracle, case):
+    """Walls (ABB, IABB on a disc), EQ nodes with and without cut links, an EQ
+    inlet and an outlet column (channel), with a prescribed Poiseuille
+    velocity: the gradient of J from the probed adjoint equals central
+    differences of the forward oracle (J is quadratic in Q)."""
     nx, ny, T = 16, 12, 10
-    flags, q, groups, u = W.walled_box(nx, ny, 6.3, 5.6, 2.2)
+    if case == "walled":
+        flags, q, groups, u = W.walled_box(nx, ny, 6.3, 5.6, 2.2)
+    else:
+        flags, q, groups, u = W.channel(nx, ny, 6.3, 5.6, 2.2, H_wall=0.5)
     n = nx * ny
     rng = np.random.default_rng(43)
     src = 0.01 * rng.standard_normal(n)
@@ -120,6 +125,9 @@ def test_dense_adjoint_with_walls_vs_central_differences(oracle):
     fluid = np.nonzero(t == W.FLUID)[0]
     eqs = np.nonzero(t == W.EQ)[0]
     nodes = list(rng.choice(fluid, 5, replace=False)) + [int(eqs[0]), int(eqs[-1])]
+    outs = np.nonzero(t == W.OUTLET)[0]
+    if outs.size:
+        nodes += [int(outs[1]), int(outs[-2]), int(outs[1]) - 1]
     eps = 1e-3
     for node in nodes:
         qp = src.copy()
