@@ -201,6 +201,59 @@ def test_gradient_with_walls_matches_oracle(L, oracle):
     assert rel_l2(qt.grad.cpu().numpy(), go) < 1e-11
 
 
+def test_walls_gradient_vs_central_differences(L):
+    """Walled box with a disc and EQ nodes, 96 x 48, 300 steps: the FP32
+    adjoint gradient (checkpoints every 17 steps) matches FP64 central
+    differences (eps = 1e-3) of the GPU forward on 10 nodes (fluid nodes next
+    to the walls and the disc, and EQ nodes) within 1e-4 relative L2."""
+    import torch
+    from paper_2203_01316_amd import workloads as W
+    from paper_2203_01316_amd.adjoint import source_objective
+    nx, ny, T = 96, 48, 300
+    flags, q, groups, u = W.walled_box(nx, ny, 30.3, 22.6, 8.2)
+    n = nx * ny
+    rng = np.random.default_rng(54)
+    src = 0.01 * rng.standard_normal(n)
+    target = 1.0 + 0.01 * rng.standard_normal(n)
+    H0 = np.ones(n)
+    t = flags & 15
+    near = np.nonzero((t == W.FLUID) & ((np.arange(n) // nx == 1) | (np.arange(n) // nx == ny - 2)))[0]
+    nodes = list(rng.choice(near, 4, replace=False)) + list(rng.choice(np.nonzero(t == W.FLUID)[0], 4,
+                                                                         replace=False))
+    eqs = np.nonzero(t == W.EQ)[0]
+    nodes += [int(eqs[0]), int(eqs[-1])]
+
+    def ctx(storage):
+        g = L.LBM(9, nx, ny, storage=storage, k=0.02, with_source=True, u_mode=1, flags=flags, q=q, groups=groups)
+        g.set_velocity(f32(u) if storage == "fp32" else u)
+        return g
+
+    g32 = ctx("fp32")
+    qt = torch.tensor(f32(src), dtype=torch.float32, device=g32.device, requires_grad=True)
+    J = source_objective(qt, g32, H0, target, T, interval=17, recompute=True)
+    J.backward()
+    adj = qt.grad.double().cpu().numpy()[nodes]
+    g64 = ctx("fp64")
+    eps = 1e-3
+
+    def J64(qv):
+        g64.set_source(qv)
+        g64.init(H0)
+        g64.step(T)
+        Jv, _, _ = g64.objective(target)
+        return Jv
+
+    fd = []
+    for m in nodes:
+        qp = src.copy()
+        qp[m] += eps
+        qm = src.copy()
+        qm[m] -= eps
+        fd.append((J64(qp) - J64(qm)) / (2 * eps))
+    fd = np.array(fd)
+    assert rel_l2(adj, fd) < 1e-4, (adj, fd)
+
+
 def test_adjoint_rejects_flow(L):
     """The hydrodynamic lattice has no adjoint."""
     import torch
