@@ -898,28 +898,37 @@ __global__ void __launch_bounds__(256) k_adjoint(const KArgs a, const R *lam_nex
 }
 
 // Discrete adjoint of the advection-diffusion step with geometry (walls
-// ABB/IABB of Eq. IABB, EQ nodes, outlets), in three passes over lam_prev:
-//  1. mu_i(y) = lam_next_i(y + e_i) where node y + e_i pulls h*_i(y) (not
-//     solid, not an EQ node, not the e_x < 0 populations of a bulk outlet),
-//     plus the copy of a bulk outlet whose upstream node y + e_i is;
-//  2. per boundary-node record, the transpose of its wall rules; for a listed
-//     EQ node or outlet, the removal of pass-1 terms that are not pulls, and
-//     for an outlet the transpose of its copy;
-//  3. the transposed collision of each node in place; dJdQ(y) += b^T mu.
-// Pass 2 adds with atomics: two walls one node apart can feed one entry.
+// ABB/IABB of Eq. IABB, EQ nodes, outlets).  With mu = S^T lam_next (the
+// transpose of streaming with the wall rules), lam_prev = C^T mu node by
+// node, and C^T is linear, so:
+//  1. k_adj_bulk gathers mu_i(y) = lam_next_i(y + e_i) where node y + e_i
+//     pulls h*_i(y) (not solid, not an EQ node, not the e_x < 0 populations
+//     of a bulk outlet, plus the copy of a bulk outlet whose upstream node
+//     y + e_i is) and applies C^T in registers, as the periodic kernel;
+//  2. k_adj_fix walks the boundary-node list.  Each record lists the terms
+//     of mu that pass 1 got wrong (its wall rules; for a listed EQ node or
+//     outlet the gathered terms that are not pulls, and for an outlet the
+//     transpose of its copy), and adds C^T of each term to lam_prev of the
+//     node it belongs to, with atomics: two records can share a node.
 template <int Q, class R>
-__global__ void __launch_bounds__(256) k_adj_gather(const KArgs a, const R *lam_next, R *mu) {
+__global__ void __launch_bounds__(256) k_adj_bulk(const KArgs a, const R *lam_next, R *lam_prev, double *dJdQ) {
+  constexpr int D = Lat<Q>::D;
   const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (m >= a.n) return;
-  const bool solid = a.cls[m] == CLS_SOLID;
+  if (a.cls[m] == CLS_SOLID) {
+#pragma unroll
+    for (int i = 0; i < Q; i++) lam_prev[(int64_t)i * a.n + m] = R(0);
+    return;
+  }
   const Node c = coords<Q>(a, m);
+  R g[Q];
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     const int64_t d = shifted<Q>(a, c, i, +1);
     const uint8_t cd = a.cls[d];
     // a bulk outlet copies its e_x < 0 populations from node x - 1 instead
     const bool copied = Lat<Q>::ex(i) < 0 && cd == CLS_OUTLET;
-    const bool pulled = !solid && cd != CLS_SOLID && cd < CLS_EQ && !copied;
+    const bool pulled = cd != CLS_SOLID && cd < CLS_EQ && !copied;
     R v = pulled ? lam_next[(int64_t)i * a.n + d] : R(0);
     if (Lat<Q>::ex(i) < 0 && pulled && cd == CLS_BULK) {
       // node d + e_x may be a bulk outlet that copies h_i(d) = h*_i(m)
@@ -927,96 +936,100 @@ __global__ void __launch_bounds__(256) k_adj_gather(const KArgs a, const R *lam_
       if constexpr (Lat<Q>::D == 3) d2 += c.Z[1 + Lat<Q>::ez(i)];
       if (a.cls[d2] == CLS_OUTLET) v += lam_next[(int64_t)i * a.n + d2];
     }
-    mu[(int64_t)i * a.n + m] = v;
+    g[Lat<Q>::slot(i)] = v;
   }
-}
-
-// Transpose of the wall rule that writes h_o(x) from h*_i(x), h*_o(x) and the
-// pulled h*_i(x - e_i) (o = opp(i)), applied to the adjoint lo of h_o(x).
-template <int Q, class R>
-__device__ __forceinline__ void adj_wall(const KArgs &a, const Node &c, int64_t m, int i, const DevWall<R> &w, R lo,
-                                         R *mu) {
-  const int o = Lat<Q>::opp(i);
-  if (!(w.interp & 2)) {
-    atomicAdd(mu + (int64_t)i * a.n + m, -lo);
-  } else if (w.q <= R(0.5)) {
-    atomicAdd(mu + (int64_t)i * a.n + m, -R(2) * w.q * lo);
-    atomicAdd(mu + (int64_t)i * a.n + shifted<Q>(a, c, i, -1), -(R(1) - R(2) * w.q) * lo);
-  } else {
-    atomicAdd(mu + (int64_t)i * a.n + m, -lo / (R(2) * w.q));
-    atomicAdd(mu + (int64_t)o * a.n + m, (R(2) * w.q - R(1)) * lo / (R(2) * w.q));
-  }
-}
-
-template <int Q, class R>
-__global__ void __launch_bounds__(64) k_adj_walls(const KArgs a, const R *lam_next, R *mu) {
-  const int64_t r = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (r >= a.nspecial) return;
-  const DevSpecial sp = a.special[r];
-  const int64_t m = sp.node;
-  const Node c = coords<Q>(a, m);
-  if (sp.type == NODE_EQ) {
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-      const int64_t y = shifted<Q>(a, c, i, -1);
-      if (a.cls[y] == CLS_SOLID) continue;
-      atomicAdd(mu + (int64_t)i * a.n + y, -lam_next[(int64_t)i * a.n + m]);
-    }
-    return;
-  }
-  const bool outlet = sp.type == NODE_OUTLET;
-  const DevWall<R> *walls = static_cast<const DevWall<R> *>(a.walls);
-  int l = sp.lb;
-#pragma unroll
-  for (int i = 1; i < Q; i++) {
-    if (!((sp.mask >> i) & 1u)) continue;
-    const DevWall<R> w = walls[l++];
-    const int o = Lat<Q>::opp(i);
-    // an outlet's e_x < 0 populations are copied, not taken from its walls
-    if (outlet && Lat<Q>::ex(o) < 0) continue;
-    adj_wall<Q, R>(a, c, m, i, w, lam_next[(int64_t)o * a.n + m], mu);
-  }
-  if (!outlet) return;
-  // h_j(x_o) = h_j(u) for e_x < 0, u = x_o - 1: the gather took lam_j(x_o) as
-  // a pull, which it is not; it goes to what h_j(u) came from instead
-  const int64_t u = c.x == 0 ? m + a.nx - 1 : m - 1;
-  const Node cu = coords<Q>(a, u);
-#pragma unroll
-  for (int j = 0; j < Q; j++) {
-    if (Lat<Q>::ex(j) >= 0) continue;
-    const R lx = lam_next[(int64_t)j * a.n + m];
-    const int64_t y = shifted<Q>(a, c, j, -1);
-    if (a.cls[y] != CLS_SOLID) atomicAdd(mu + (int64_t)j * a.n + y, -lx);
-    const int i = Lat<Q>::opp(j);
-    if ((sp.umask >> i) & 1u) {
-      // h_j(u) is the wall rule of u's cut link i
-      const DevWall<R> w = walls[sp.ub + __popc(sp.umask & ((1u << i) - 1u))];
-      adj_wall<Q, R>(a, cu, u, i, w, lx, mu);
-    } else {
-      atomicAdd(mu + (int64_t)j * a.n + shifted<Q>(a, cu, j, -1), lx);
-    }
-  }
-}
-
-template <int Q, class R>
-__global__ void __launch_bounds__(256) k_adj_collide(const KArgs a, R *lam, double *dJdQ) {
-  constexpr int D = Lat<Q>::D;
-  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (m >= a.n) return;
-  if (a.cls[m] == CLS_SOLID) {
-#pragma unroll
-    for (int i = 0; i < Q; i++) lam[(int64_t)i * a.n + m] = R(0);
-    return;
-  }
-  R g[Q];
-#pragma unroll
-  for (int i = 0; i < Q; i++) g[Lat<Q>::slot(i)] = lam[(int64_t)i * a.n + m];
   R ux, uy, uz;
   prescribed_u<Q, R>(a, m, ux, uy, uz);
   const R dq = collide_adjoint<D, R>(g, rates<R>(a, false), ux, uy, uz);
 #pragma unroll
-  for (int i = 0; i < Q; i++) lam[(int64_t)i * a.n + m] = g[Lat<Q>::slot(i)];
+  for (int i = 0; i < Q; i++) lam_prev[(int64_t)i * a.n + m] = g[Lat<Q>::slot(i)];
   if (dJdQ) dJdQ[m] += double(dq);
+}
+
+// One term v of mu_k(node) missed or mis-taken by k_adj_bulk.
+template <class R>
+struct AdjTerm {
+  int64_t node;
+  int32_t k;
+  R v;
+};
+
+// Terms of the wall rule that writes h_o(x) from h*_i(x), h*_o(x) and the
+// pulled h*_i(x - e_i) (o = opp(i)), for the adjoint lo of h_o(x).
+template <int Q, class R>
+__device__ __forceinline__ void adj_wall_terms(const KArgs &a, const Node &c, int64_t m, int i, const DevWall<R> &w,
+                                               R lo, AdjTerm<R> *t, int &nt) {
+  const int o = Lat<Q>::opp(i);
+  if (!(w.interp & 2)) {
+    t[nt++] = {m, i, -lo};
+  } else if (w.q <= R(0.5)) {
+    t[nt++] = {m, i, -R(2) * w.q * lo};
+    t[nt++] = {shifted<Q>(a, c, i, -1), i, -(R(1) - R(2) * w.q) * lo};
+  } else {
+    t[nt++] = {m, i, -lo / (R(2) * w.q)};
+    t[nt++] = {m, o, (R(2) * w.q - R(1)) * lo / (R(2) * w.q)};
+  }
+}
+
+// One thread per (boundary-node record, direction dir): the terms of that
+// direction (as the cut link dir, and for an outlet as the copied direction
+// dir), so that the few terms of a record spread over Q threads.
+template <int Q, class R>
+__global__ void __launch_bounds__(256) k_adj_fix(const KArgs a, const R *lam_next, R *lam_prev, double *dJdQ) {
+  constexpr int D = Lat<Q>::D;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= a.nspecial * Q) return;
+  const int64_t r = idx / Q;
+  const int dir = (int)(idx - r * Q);
+  const DevSpecial sp = a.special[r];
+  const int64_t m = sp.node;
+  const Node c = coords<Q>(a, m);
+  AdjTerm<R> t[5];
+  int nt = 0;
+  if (sp.type == NODE_EQ) {
+    // pass 1 gathered lam_dir(x_eq) into a neighbour, but EQ nodes pull nothing
+    const int64_t y = shifted<Q>(a, c, dir, -1);
+    if (a.cls[y] != CLS_SOLID) t[nt++] = {y, dir, -lam_next[(int64_t)dir * a.n + m]};
+  } else {
+    const bool outlet = sp.type == NODE_OUTLET;
+    const DevWall<R> *walls = static_cast<const DevWall<R> *>(a.walls);
+    const int o = Lat<Q>::opp(dir);
+    // an outlet's e_x < 0 populations are copied, not taken from its walls
+    if (((sp.mask >> dir) & 1u) && !(outlet && Lat<Q>::ex(o) < 0)) {
+      const DevWall<R> w = walls[sp.lb + __popc(sp.mask & ((1u << dir) - 1u))];
+      adj_wall_terms<Q, R>(a, c, m, dir, w, lam_next[(int64_t)o * a.n + m], t, nt);
+    }
+    if (outlet && Lat<Q>::ex(dir) < 0) {
+      // h_dir(x_o) = h_dir(u), u = x_o - 1: pass 1 took lam_dir(x_o) as a
+      // pull, which it is not; it goes to what h_dir(u) came from instead
+      const int j = dir;
+      const int64_t u = c.x == 0 ? m + a.nx - 1 : m - 1;
+      const Node cu = coords<Q>(a, u);
+      const R lx = lam_next[(int64_t)j * a.n + m];
+      const int64_t y = shifted<Q>(a, c, j, -1);
+      if (a.cls[y] != CLS_SOLID) t[nt++] = {y, j, -lx};
+      const int i = Lat<Q>::opp(j);
+      if ((sp.umask >> i) & 1u) {
+        // h_j(u) is the wall rule of u's cut link i
+        const DevWall<R> w = walls[sp.ub + __popc(sp.umask & ((1u << i) - 1u))];
+        adj_wall_terms<Q, R>(a, cu, u, i, w, lx, t, nt);
+      } else {
+        t[nt++] = {shifted<Q>(a, cu, j, -1), j, lx};
+      }
+    }
+  }
+  for (int e = 0; e < nt; e++) {
+    const AdjTerm<R> te = t[e];
+    R g[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) g[Lat<Q>::slot(i)] = i == te.k ? te.v : R(0);
+    R ux, uy, uz;
+    prescribed_u<Q, R>(a, te.node, ux, uy, uz);
+    const R dq = collide_adjoint<D, R>(g, rates<R>(a, false), ux, uy, uz);
+#pragma unroll
+    for (int i = 0; i < Q; i++) atomicAdd(lam_prev + (int64_t)i * a.n + te.node, g[Lat<Q>::slot(i)]);
+    if (dJdQ) atomicAdd(dJdQ + te.node, double(dq));
+  }
 }
 
 // Objective J = 1/2 sum (H - H*)^2 over the non-solid nodes (solid nodes
@@ -1165,13 +1178,9 @@ static hipError_t adjoint_t(const KArgs &a, const void *ln, void *lp, void *dq, 
     k_adjoint<Q, R><<<blocks_for(a.n, 256), 256, 0, s>>>(a, lam_next, lam_prev, dJdQ);
     return hipGetLastError();
   }
-  k_adj_gather<Q, R><<<blocks_for(a.n, 256), 256, 0, s>>>(a, lam_next, lam_prev);
+  k_adj_bulk<Q, R><<<blocks_for(a.n, 256), 256, 0, s>>>(a, lam_next, lam_prev, dJdQ);
   if (hipError_t e = hipGetLastError()) return e;
-  if (a.nspecial > 0) {
-    k_adj_walls<Q, R><<<blocks_for(a.nspecial, 64), 64, 0, s>>>(a, lam_next, lam_prev);
-    if (hipError_t e = hipGetLastError()) return e;
-  }
-  k_adj_collide<Q, R><<<blocks_for(a.n, 256), 256, 0, s>>>(a, lam_prev, dJdQ);
+  if (a.nspecial > 0) k_adj_fix<Q, R><<<blocks_for(a.nspecial * Q, 256), 256, 0, s>>>(a, lam_next, lam_prev, dJdQ);
   return hipGetLastError();
 }
 
