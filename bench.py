@@ -206,7 +206,40 @@ def leg_adjoint(torch, L, np, n1=512, steps=2000, interval=45):
     adj = e0.elapsed_time(e1) / 1e3 / (2 * (steps // 2))
     out["kernels"] = {"forward_us_per_step": round(fwd * 1e6, 2), "adjoint_us_per_step": round(adj * 1e6, 2),
                       "ratio": round(adj / fwd, 3)}
+    out["walls"] = leg_adjoint_walls(torch, L, np, n1, steps)
     return out
+
+
+def leg_adjoint_walls(torch, L, np, n1, steps):
+    """Kernel-only adjoint/forward ratio of the same lattice with walls: a
+    channel periodic in x with ABB walls, an IABB disc and EQ nodes."""
+    from paper_2203_01316_amd import workloads as W
+
+    flags, q, groups, u = W.walled_box(n1, n1, 0.3 * n1, 0.45 * n1, 0.15 * n1)
+    n = n1 * n1
+    g = L.LBM(L.D2Q9, n1, n1, storage="fp32", k=0.01, with_source=True, u_mode=1, flags=flags, q=q,
+              groups=groups)
+    g.set_velocity(np.asarray(u, np.float32))
+    g.set_source(np.zeros(n, np.float32))
+    g.init(np.ones(n))
+    fwd = time_steps(torch, g, steps, 20)
+    lam = torch.zeros(9, n, dtype=torch.float32, device=g.device)
+    other = torch.empty_like(lam)
+    dq = torch.zeros(n, dtype=torch.float64, device=g.device)
+    for _ in range(20):
+        g.adjoint_step(lam, other, dq)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps // 2):
+        g.adjoint_step(lam, other, dq)
+        g.adjoint_step(other, lam, dq)
+    e1.record()
+    torch.cuda.synchronize()
+    adj = e0.elapsed_time(e1) / 1e3 / (2 * (steps // 2))
+    return {"workload": f"d2q9_ade_walled_box_{n1}x{n1}", "forward_us_per_step": round(fwd * 1e6, 2),
+            "adjoint_us_per_step": round(adj * 1e6, 2), "ratio": round(adj / fwd, 3)}
 
 
 def cpu_baseline(inputs, steps, single_thread=True):
