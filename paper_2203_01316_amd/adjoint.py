@@ -2,7 +2,8 @@
 advection-diffusion lattice, as a torch.autograd.Function over liblbm.so.
 
 Forward: T steps of the HIP step kernel with the source Q (App. D) as the
-context's source field, then J = 1/2 sum (H_T - H*)^2 (lbm_objective).
+context's source field, then J = 1/2 sum (H_T - H*)^2 over the non-solid
+nodes (lbm_objective).
 Backward: T reverse steps of the HIP adjoint kernel (lbm_adjoint_step), the
 exact transpose of the forward step, accumulating dJ/dQ.
 
