@@ -143,3 +143,22 @@ def test_dense_adjoint_with_walls_vs_central_differences(oracle, case):
         fd = (Jp - Jm) / (2 * eps)
         assert fd == pytest.approx(g[node], rel=1e-7, abs=1e-12), node
     assert J > 0
+
+
+def test_dense_adjoint_ignores_solid_nodes(oracle):
+    """Solid nodes carry no state: lambda there is ignored on input and zero on
+    output."""
+    nx, ny = 12, 10
+    flags, q, groups, u = W.walled_box(nx, ny, 4.3, 4.6, 1.8)
+    n = nx * ny
+    sim = oracle.Sim(9, nx, ny, s_h=oracle.preset(9, "trt", oracle.s_main(0.02)), uvel=u, src=np.zeros(n),
+                     flags=flags, qlink=q, groups=groups)
+    rng = np.random.default_rng(44)
+    lam = rng.standard_normal((9, n))
+    solid = (flags & 15) == W.SOLID
+    lam2 = lam.copy()
+    lam2[:, solid] = rng.standard_normal((9, int(solid.sum())))
+    a1 = sim.adjoint_step_dense(lam)
+    a2 = sim.adjoint_step_dense(lam2)
+    assert np.array_equal(a1, a2)
+    assert not a1[:, solid].any()
