@@ -1103,8 +1103,9 @@ static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b -
 // us at 2 blocks per CU against 1235 uncapped (AA: 1266 against 1369), the
 // order-limited cumulant step 1192 at 2 against 1218 at 3 and 1244 at 4 (AA:
 // 1273 against 1326 at 3); at 2048^2 the D2Q9 two-array step takes 97.2 us
-// at 3 against 100.9.  The D2Q9 AA layout, FP16 storage and the full
-// cumulant transform measured no gain or a loss.  0 = no cap.
+// at 3 against 100.9, and with FP64 storage 196.1 at 2 against 203.5.  The
+// D2Q9 AA layout, FP16 storage, the FP64 D3Q27 steps and the full cumulant
+// transform measured no gain or a loss.  0 = no cap.
 constexpr size_t lds_for_blocks(int blocks) { return (size_t)(160 * 1024) / (blocks + 1) + 1024; }
 
 template <int Q, int ST, int LAY, int CU>
@@ -1112,6 +1113,7 @@ constexpr size_t step_lds() {
   constexpr bool fp32 = (ST == ST_FP32 || ST == ST_FP32_DEV) && (CU == 0 || (CU & 4));
   if constexpr (Q == 27 && fp32) return lds_for_blocks(2);
   if constexpr (Q == 9 && fp32 && LAY == LAY_AB) return lds_for_blocks(3);
+  if constexpr (Q == 9 && ST == ST_FP64 && LAY == LAY_AB && (CU == 0 || (CU & 4))) return lds_for_blocks(2);
   return 0;
 }
 
