@@ -136,11 +136,12 @@ def test_channel_full_size_one_step(L, oracle):
 # ---------------------------------------------------------------------------
 # Coupled flow + heat with a heated cylinder (IBB / IABB, EQ inlet, outlet)
 # ---------------------------------------------------------------------------
-def _cylinder(L, oracle, nx, ny, r, storage, nu=0.04, k=0.06, oracle_init=True):
+def _cylinder(L, oracle, nx, ny, r, storage, nu=0.04, k=0.06, oracle_init=True, stream="ab", cu=False):
     flags, q, groups, u, rho0, H0 = W.heated_cylinder(nx, ny, r, u_in=0.04, amp=1e-3, seed=0)
     return pair(L, oracle, Q=9, dims=(nx, ny, 1), storage=storage, with_ns=True, nu=nu, k=k, uvel=u,
                 flags=flags, q=q, groups=groups, H0=H0, u_init=f32(u) if storage != "fp64" else u,
-                rho0=rho0, oracle_init=oracle_init)
+                rho0=rho0, oracle_init=oracle_init, stream=L.STREAM_AA if stream == "aa" else L.STREAM_AB,
+                relax_h="1st" if cu else "trt", cu_f=cu, cu_h=cu)
 
 
 @pytest.mark.parametrize("storage,tol", [("fp64", TOL64), ("fp32", TOL32)])
@@ -186,10 +187,15 @@ def test_boundary_mix_coupled(L, oracle, storage, tol):
         assert red[3 + j] == pytest.approx(o.section_flux(X, ho), rel=max(tol, 1e-11) * 10, abs=1e-12)
 
 
-def test_cylinder_full_size_one_step(L, oracle):
-    """2048^2 coupled FP32 (the benchmark configuration): one GPU step equals
-    the oracle's step from the same stored state at every node."""
-    g, o = _cylinder(L, oracle, 2048, 2048, 64, "fp32", nu=0.0512, k=0.0512 / 0.71, oracle_init=False)
+@pytest.mark.parametrize("cu", [False, True], ids=["cm", "cumulant"])
+@pytest.mark.parametrize("stream", ["ab", "aa"])
+def test_cylinder_full_size_one_step(L, oracle, cu, stream):
+    """2048^2 coupled FP32, in the benchmark's configurations (CM-NS f with
+    CM-TRT h, or the cumulant f with Cumulants-1st h; two-array or in-place
+    layout): one GPU step equals the oracle's step from the same stored state
+    at every node."""
+    g, o = _cylinder(L, oracle, 2048, 2048, 64, "fp32", nu=0.0512, k=0.0512 / 0.71, oracle_init=False,
+                     stream=stream, cu=cu)
     g.step(20)
     o.set_post(f=gpu_post(g, "f"), h=gpu_post(g, "h"), t=g.t)
     g.step(1)
@@ -216,13 +222,18 @@ def test_d3q27_tgv_small(L, oracle, storage, tol):
     assert rel_l2(gpu_pre(g, "h"), ho) < tol
 
 
-def test_d3q27_full_size_sampled(L, oracle):
-    """256^3 FP32: one GPU step equals the oracle's node collision applied to
-    the pulled neighbourhood, on 2000 sampled nodes; mass is conserved."""
+@pytest.mark.parametrize("cu", [False, True], ids=["cm", "cumulant"])
+@pytest.mark.parametrize("stream", ["ab", "aa"])
+def test_d3q27_full_size_sampled(L, oracle, cu, stream):
+    """256^3 FP32, in the benchmark's configurations (CM-NS f with CM-TRT h,
+    or the cumulant f with Cumulants-1st h; two-array or in-place layout):
+    one GPU step equals the oracle's node collision applied to the pulled
+    neighbourhood, on 2000 sampled nodes; mass is conserved."""
     import torch
     n1 = 256
     rho, u, H = W.taylor_green_3d(n1, 0.04)
-    g = L.LBM(27, n1, n1, n1, with_ns=True, storage="fp32", nu=0.002, k=0.002, relax_h="trt")
+    g = L.LBM(27, n1, n1, n1, with_ns=True, storage="fp32", nu=0.002, k=0.002, relax_h="1st" if cu else "trt",
+              cumulant_f=cu, cumulant_h=cu, stream=L.STREAM_AA if stream == "aa" else L.STREAM_AB)
     g.init(H, u=u, rho=rho)
     del rho, u, H
     g.step(5)
@@ -249,8 +260,9 @@ def test_d3q27_full_size_sampled(L, oracle):
     for j in range(len(nodes)):
         r = pf[:, j].sum()
         uu = (e.T.astype(float) @ pf[:, j]) / r
-        of[:, j] = oracle.collide_node(27, pf[:, j], uu, sf)
-        oh[:, j] = oracle.collide_node(27, ph[:, j], uu, sh)
+        collide = oracle.collide_node_cu if cu else oracle.collide_node
+        of[:, j] = collide(27, pf[:, j], uu, sf)
+        oh[:, j] = collide(27, ph[:, j], uu, sh)
     assert rel_l2(qf, of) < TOL32
     assert rel_l2(qh, oh) < TOL32
 
