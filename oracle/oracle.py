@@ -1,4 +1,4 @@
-"""Python driver of the FP64 CPU oracle (``lbm_oracle.c``).
+"""Python binding of the FP64 CPU oracle (``lbm_oracle.c``).
 
 TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
 CPU-baseline leg use it to check and time the GPU library.  Nothing in the
