@@ -135,11 +135,6 @@ __device__ __forceinline__ global_ptr<E> uniform_base(E *p) {
   return (global_ptr<E>)v;
 }
 
-template <int Q, class S, int NL>
-__device__ __forceinline__ int64_t pop_index(int slot, int64_t ps, int64_t m) {
-  return slot_offset<Q, S>(slot, ps) + (int64_t)node_offset<Q, S, NL>(ps, m);
-}
-
 // Load / store population i (stored in slot `slot`) of node m; ps is the
 // slots per tile (FP64/FP32) or the plane stride (FP16) of the layout.  The
 // deviation storages keep g_i - w_i g_ref; w_i = w_opp(i), so a swapped slot
