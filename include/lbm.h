@@ -146,8 +146,11 @@ typedef struct {
 
 /* One cut link (Sec. 3): boundary node x_b, direction dir from x_b towards the
  * wall (x_b + e_dir is SOLID), group of that solid node, xf_solid = 1 when
- * x_f = x_b - e_dir is solid (interpolation then skipped, q taken as 1/2), and
- * q in (0, 1] the wall distance as a fraction of e_dir.  Sorted by (node, dir). */
+ * x_f = x_b - e_dir is solid (a one-node gap), and q in (0, 1] the wall
+ * distance as a fraction of e_dir.  In a gap, a link with q < 1/2 takes the
+ * plain (A)BB rule, since the q <= 1/2 branch of Eqs. IBB and IABB reads x_f;
+ * a link with q > 1/2 keeps the interpolated rule, whose branch reads only
+ * x_b.  Sorted by (node, dir). */
 typedef struct {
   int32_t node;
   int32_t dir;

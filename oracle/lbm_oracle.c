@@ -517,7 +517,7 @@ typedef struct {
   int32_t node;
   int32_t dir;   /* direction from the boundary node towards the wall */
   int32_t group;
-  int32_t xf_solid; /* 1 when x_b - e_dir is solid: interpolation is skipped */
+  int32_t xf_solid; /* 1 when x_b - e_dir is solid: below q = 1/2 the rule is plain (A)BB */
   double q;
 } ora_link;
 
@@ -645,7 +645,7 @@ long ora_links(const ora_cfg *c, ora_link *out, long cap) {
 }
 
 /* Interpolated bounce-back (Eq. IBB) for f; q = 1/2 without interpolation
- * (plain BB) or when x_f is solid. */
+ * (plain BB), or when the q <= 1/2 branch would need x_f and x_f is solid. */
 static double ibb(double q, double gb_i, double gb_opp, double gf_i) {
   if (q <= 0.5) return 2.0 * q * gb_i + (1.0 - 2.0 * q) * gf_i;
   return (gb_i + (2.0 * q - 1.0) * gb_opp) / (2.0 * q);
@@ -712,12 +712,14 @@ int ora_stream(const ora_cfg *c, const double *fs, const double *hs, double *f, 
     long xf = neighbour(c, b, C.L.e[a], -1);
     double q = k->q;
     if (c->with_ns) {
-      double qf = (G->f_scheme == ORA_BB || k->xf_solid) ? 0.5 : q;
+      /* the q > 1/2 branch reads only x_b, so a solid x_f (one-node gap)
+       * forces plain bounce-back only below q = 1/2 */
+      double qf = (G->f_scheme == ORA_BB || (k->xf_solid && q < 0.5)) ? 0.5 : q;
       f[o * N + b] = ibb(qf, fs[a * N + b], fs[o * N + b], fs[a * N + xf]);
     }
     {
       double u[3], rho, geq[ORA_MAXQ];
-      double qh = (G->h_scheme == ORA_ABB || k->xf_solid) ? 0.5 : q;
+      double qh = (G->h_scheme == ORA_ABB || (k->xf_solid && q < 0.5)) ? 0.5 : q;
       if (c->with_ns)
         moments_f(&C.L, fs, N, b, &rho, u);
       else

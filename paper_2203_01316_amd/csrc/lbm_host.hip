@@ -374,9 +374,12 @@ bool build_geometry_q(const lbm_params *p, const uint16_t *flags, const double *
 }
 
 // Per-link wall records in the arithmetic type R.  A link takes the plain
-// (anti-)bounce-back rule when its group asks for it, when x_f = x_b - e_i is
-// solid (one-node gap) or when q = 1/2, where both branches of the
-// interpolated rules reduce to it (Sec. 3).
+// (anti-)bounce-back rule when its group asks for it, when q = 1/2, where both
+// branches of the interpolated rules reduce to it, and when the q <= 1/2
+// branch (the only one that reads x_f = x_b - e_i) meets a solid x_f (a
+// one-node gap).  The q > 1/2 branch reads x_b only and stays interpolated
+// in a gap (Sec. 3, Eqs. IBB and IABB).  The branch test is made on q as the
+// kernels see it, in R.
 template <class R>
 void wall_records(const std::vector<DevLink> &links, const std::vector<DevGroup> &groups, std::vector<char> *out) {
   out->assign(sizeof(DevWall<R>) * links.size(), 0);
@@ -384,7 +387,7 @@ void wall_records(const std::vector<DevLink> &links, const std::vector<DevGroup>
   for (size_t l = 0; l < links.size(); l++) {
     const DevLink &k = links[l];
     const DevGroup &g = groups[k.group];
-    const bool plain = k.xf_solid || k.q == 0.5;
+    const bool plain = k.q == 0.5 || (k.xf_solid && R(k.q) <= R(0.5));
     w[l].q = R(k.q);
     w[l].H_w = R(g.H_w);
     w[l].interp = (g.f_scheme == LBM_WALL_IBB && !plain ? 1 : 0) | (g.h_scheme == LBM_WALL_IABB && !plain ? 2 : 0);

@@ -194,6 +194,42 @@ def walled_box(nx: int = 24, ny: int = 14, cx: float = 8.3, cy: float = 6.6, r: 
     return f2.reshape(-1), q, groups, u
 
 
+def gap_box(nx: int = 20, ny: int = 16, H_w: float = 1.7, seed: int = 5, Q: int = 9):
+    """Periodic box with two one-node gaps, so that cut links have a solid x_f:
+    a horizontal slit (solid rows y = ny/4 and ny/4 + 2 for nx/8 <= x < 3nx/4,
+    fluid row between them) and a vertical one (solid columns x = 0.8nx and
+    0.8nx + 2 for ny/2 <= y < 7ny/8).  All solid nodes are group 0 (IBB/IABB,
+    H = H_w).  Returns (flags, q_lo, q_hi, groups): q_lo holds seeded uniform
+    wall distances in [0.1, 0.45] on every cut link, q_hi in [0.55, 1]
+    (numpy PCG64(seed)); other entries are 1/2.  For D3Q27 (Q = 27) the same
+    cross-section is extruded along z (ny/4 layers, periodic)."""
+    nz = 1 if Q == 9 else max(ny // 4, 2)
+    f = np.zeros((nz, ny, nx), np.uint16)
+    y0, x0, x1 = ny // 4, nx // 8, (3 * nx) // 4
+    f[:, y0, x0:x1] = flag(SOLID, 0)
+    f[:, y0 + 2, x0:x1] = flag(SOLID, 0)
+    xc, ya, yb = int(0.8 * nx), ny // 2, (7 * ny) // 8
+    f[:, ya:yb, xc] = flag(SOLID, 0)
+    f[:, ya:yb, xc + 2] = flag(SOLID, 0)
+    flags = f.reshape(-1)
+    n = flags.size
+    E = D2Q9_E if Q == 9 else D3Q27_E
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo = rng.uniform(0.1, 0.45, size=(Q, n))
+    hi = rng.uniform(0.55, 1.0, size=(Q, n))
+    q_lo = np.full((Q, n), 0.5)
+    q_hi = np.full((Q, n), 0.5)
+    solid = (f & 15) == SOLID
+    for a in range(1, Q):
+        ex, ey, ez = (int(v) for v in E[a])
+        cut = (~solid) & np.roll(solid, shift=(-ez, -ey, -ex), axis=(0, 1, 2))
+        cut = cut.reshape(-1)
+        q_lo[a, cut] = lo[a, cut]
+        q_hi[a, cut] = hi[a, cut]
+    groups = [dict(f_scheme=1, h_scheme=1, rho_w=1.0, H_w=H_w)]
+    return flags, q_lo, q_hi, groups
+
+
 def heated_cylinder(nx: int = 2048, ny: int = 2048, r: float = 64, cx=None, cy=None,
                     u_in: float = 0.04, amp: float = 1e-3, seed: int = 0, T_in: float = 10.0,
                     T_cyl: float = 11.0):

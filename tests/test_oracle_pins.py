@@ -291,6 +291,37 @@ def test_source_adds_Q_per_step(oracle):
     np.testing.assert_allclose(Hb - Ha, 0.1, atol=1e-14)
 
 
+def _steady_source_error(oracle, N, u, k, kind="trt", Q0=1e-3):
+    """1-D periodic lattice (N x 1), uniform velocity u along x, source
+    Q = Q0 sin(kappa x), kappa = 2 pi / N.  The advection-diffusion equation
+    H_t + u H_x = k H_xx + Q has the steady solution
+    H = 1 + Im(Q0 e^(i kappa x) / (k kappa^2 + i u kappa)).  Started from it
+    and run for six e-folds of the transient, the lattice's H = sum h + Q/2
+    differs from it by the returned relative L2 error."""
+    kap = 2 * math.pi / N
+    x = np.arange(N)
+    Ha = 1.0 + np.imag(Q0 / (k * kap * kap + 1j * u * kap) * np.exp(1j * kap * x))
+    sim = oracle.Sim(9, N, 1, s_h=oracle.preset(9, kind, oracle.s_main(k)), u0=(u, 0.0, 0.0),
+                     src=Q0 * np.sin(kap * x))
+    sim.init(Ha)
+    sim.step(int(6.0 / (k * kap * kap)))
+    _, _, H = sim.macroscopic()
+    return math.sqrt(((H - Ha) ** 2).sum() / ((Ha - 1.0) ** 2).sum())
+
+
+def test_source_steady_sinusoid_second_order(oracle):
+    """App. D carried to central moments, beyond the zeroth moment: with a
+    sinusoidal source the steady state converges at second order under
+    refinement at fixed u and k (16, 32, 64 nodes per wavelength).  Adding Q
+    without the factor (1 - s_000/2), or dropping the Q/2 from the
+    equilibrium's H, leaves an O(1) error; reporting H = sum h without the
+    Q/2 leaves a first-order one once u != 0."""
+    for u, k in ((0.1, 0.05), (0.0, 0.05)):
+        e = [_steady_source_error(oracle, N, u, k) for N in (16, 32, 64)]
+        assert e[2] < 1e-3, (u, k, e)
+        assert 3.5 < e[0] / e[1] < 4.6 and 3.5 < e[1] / e[2] < 4.6, (u, k, e)
+
+
 # ---------------------------------------------------------------------------
 # Analytic benchmarks (Sec. 4.1, 4.3)
 # ---------------------------------------------------------------------------
@@ -409,6 +440,153 @@ def test_abb_is_iabb_at_half(oracle):
         sim.step(10)
         res.append(sim.pre()[1])
     np.testing.assert_array_equal(res[0], res[1])
+
+
+def _flat_channel(nf, qb, qt, nx=1):
+    """D2Q9 channel between two flat walls, periodic in x: solid rows y = 0 and
+    y = nf + 1, nf fluid rows.  Every link from row 1 with e_y = -1 has q = qb
+    (wall at y = 1 - qb), every link from row nf with e_y = +1 has q = qt (wall
+    at y = nf + qt), so the width is W = nf - 1 + qb + qt."""
+    ny = nf + 2
+    N = nx * ny
+    flags = np.zeros((ny, nx), np.uint16)
+    flags[0, :] = W.flag(W.SOLID, 0)
+    flags[-1, :] = W.flag(W.SOLID, 0)
+    q = np.full((9, N), 0.5)
+    y = np.arange(N) // nx
+    for a in range(1, 9):
+        if W.D2Q9_E[a, 1] < 0:
+            q[a, y == 1] = qb
+        if W.D2Q9_E[a, 1] > 0:
+            q[a, y == ny - 2] = qt
+    fluid = (y > 0) & (y < ny - 1)
+    return flags.reshape(-1), q, y, fluid, 1.0 - qb, nf - 1 + qb + qt
+
+
+def _mode_rate_error(oracle, nf, qb, qt, lattice, scheme, diff=0.1):
+    """Relative error of the decay rate of the slowest mode between the walls.
+    lattice 'f': shear wave u_x = A sin(pi (y - y_w) / W) of the Navier-Stokes
+    equations, which decays as exp(-nu (pi / W)^2 t) between no-slip walls at
+    rest; lattice 'h': H = 1 + A sin(pi (y - y_w) / W) of the diffusion
+    equation between Dirichlet walls H_w = 1, decaying as exp(-k (pi / W)^2 t).
+    The rate is read between t = tau / 2 and 2 tau, tau = W^2 / (diff pi^2),
+    from the projection of the field on the mode."""
+    flags, q, y, fluid, yw, width = _flat_channel(nf, qb, qt)
+    N = y.size
+    kk = math.pi / width
+    prof = np.where(fluid, np.sin(kk * (y - yw)), 0.0)
+    if lattice == "f":
+        u = np.zeros((3, N))
+        u[0] = 1e-3 * prof
+        sim = oracle.Sim(9, 1, nf + 2, with_ns=True, s_f=oracle.preset(9, "ns", oracle.s_main(diff)),
+                         s_h=oracle.preset(9, "trt", 1.0), flags=flags, qlink=q,
+                         groups=[dict(f_scheme=scheme, h_scheme=oracle.ABB, H_w=1.0)])
+        sim.init(np.ones(N), u=u, rho=np.ones(N))
+    else:
+        sim = oracle.Sim(9, 1, nf + 2, s_h=oracle.preset(9, "trt", oracle.s_main(diff)), flags=flags,
+                         qlink=q, groups=[dict(h_scheme=scheme, H_w=1.0)])
+        sim.init(1.0 + 0.1 * prof)
+
+    def amplitude():
+        _, uu, H = sim.macroscopic()
+        v = uu[0] if lattice == "f" else H - 1.0
+        return (v[fluid] * prof[fluid]).sum() / (prof[fluid] ** 2).sum()
+
+    tau = width * width / (diff * math.pi ** 2)
+    t1, t2 = int(round(0.5 * tau)), int(round(2.0 * tau))
+    sim.step(t1)
+    a1 = amplitude()
+    sim.step(t2 - t1)
+    a2 = amplitude()
+    return math.log(a1 / a2) / (t2 - t1) / (diff * kk * kk) - 1.0
+
+
+@pytest.mark.parametrize("lattice,interp,plain", [("f", "IBB", "BB"), ("h", "IABB", "ABB")])
+def test_interpolated_walls_second_order_off_lattice(oracle, lattice, interp, plain):
+    """Sec. 3, Eqs. IBB and IABB: with walls off the half-way point (q = 0.2 and
+    0.7, then 0.35 and 0.9, so both branches act and the two walls differ), the
+    decay rate of the slowest channel mode converges at second order to the
+    analytic one; plain (A)BB, which puts the wall half-way, converges at first
+    order only.  A swapped alpha / alpha-bar, the opposite population of x_f,
+    or swapped x_b / x_f weights each leave an error of 0.6-30% at 32 rows."""
+    si, sp = getattr(oracle, interp), getattr(oracle, plain)
+    for qb, qt in ((0.2, 0.7), (0.35, 0.9)):
+        e16 = _mode_rate_error(oracle, 16, qb, qt, lattice, si)
+        e32 = _mode_rate_error(oracle, 32, qb, qt, lattice, si)
+        assert abs(e32) < 3e-4 and 3.0 < e16 / e32 < 5.0, (qb, qt, e16, e32)
+        b16 = _mode_rate_error(oracle, 16, qb, qt, lattice, sp)
+        b32 = _mode_rate_error(oracle, 32, qb, qt, lattice, sp)
+        assert abs(b32) > 3e-3 and 1.6 < b16 / b32 < 2.4, (qb, qt, b16, b32)
+
+
+def test_walls_at_half_way_are_plain_rules_both_lattices(oracle):
+    """Eqs. IBB and IABB at q = 1/2 are BB and ABB: coupled lattices with
+    non-uniform flow, the two runs agree bit for bit."""
+    L, flags, q = _box_with_disc()
+    N = L * L
+    rng = np.random.default_rng(21)
+    u = np.zeros((3, N))
+    u[0] = 0.03 + 0.01 * rng.uniform(size=N)
+    u[1] = 0.01 * rng.uniform(size=N) - 0.005
+    H0 = 1 + 0.1 * rng.uniform(size=N)
+    rho0 = 1 + 0.01 * rng.uniform(size=N)
+    res = []
+    for fs, hs in ((oracle.BB, oracle.ABB), (oracle.IBB, oracle.IABB)):
+        sim = oracle.Sim(9, L, L, with_ns=True, s_f=oracle.preset(9, "ns", 1.6),
+                         s_h=oracle.preset(9, "trt", 1.4), flags=flags, qlink=np.full((9, N), 0.5),
+                         groups=[dict(f_scheme=fs, h_scheme=hs, H_w=2.0)])
+        sim.init(H0, u=u, rho=rho0)
+        sim.step(12)
+        res.append(sim.pre())
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    np.testing.assert_array_equal(res[0][1], res[1][1])
+
+
+def test_one_node_gap_rest_state_and_branches(oracle):
+    """A one-node gap (x_f = x_b - e_i solid): the rest state with H = H_w is
+    kept for any q, and only links with q < 1/2 fall back to the plain rule
+    (the q > 1/2 branch of Eqs. IBB / IABB reads x_b alone).  Pinned against
+    the plain rule: a gap with every q above 1/2 differs from BB/ABB, one with
+    every q below 1/2 equals it bit for bit."""
+    flags, q_lo, q_hi, groups = W.gap_box(20, 16)
+    N = flags.size
+    fluid = (flags & 15) != W.SOLID
+    for q in (q_lo, q_hi):
+        sim = oracle.Sim(9, 20, 16, with_ns=True, s_f=oracle.preset(9, "ns", 1.5),
+                         s_h=oracle.preset(9, "trt", 1.7), flags=flags, qlink=q, groups=groups)
+        sim.init(np.full(N, 1.7), u=np.zeros((3, N)), rho=np.ones(N))
+        sim.step(30)
+        f, h = sim.pre()
+        w = oracle.equilibrium(9, 1.0, [0, 0, 0])[:, None]
+        np.testing.assert_allclose(f[:, fluid], np.broadcast_to(w, f[:, fluid].shape), atol=1e-14)
+        np.testing.assert_allclose(h[:, fluid], 1.7 * np.broadcast_to(w, h[:, fluid].shape), atol=1e-14)
+    links = oracle.Sim(9, 20, 16, flags=flags, qlink=q_lo, groups=groups).links()
+    gap = links["xf_solid"] == 1
+    assert gap.sum() >= 8
+    rng = np.random.default_rng(22)
+    H0 = 1 + 0.1 * rng.uniform(size=N)
+    u = np.zeros((3, N))
+    u[0] = 0.02
+    for q, same in ((q_lo, True), (q_hi, False)):
+        out = []
+        for plain in (True, False):
+            g = [dict(gr, f_scheme=oracle.BB if plain else oracle.IBB,
+                      h_scheme=oracle.ABB if plain else oracle.IABB) for gr in groups]
+            qq = q.copy()
+            # links outside the gap take q = 1/2 so that only gap links differ
+            for ln in links[~gap]:
+                qq[ln["dir"], ln["node"]] = 0.5
+            sim = oracle.Sim(9, 20, 16, with_ns=True, s_f=oracle.preset(9, "ns", 1.5),
+                             s_h=oracle.preset(9, "trt", 1.7), flags=flags, qlink=qq, groups=g)
+            sim.init(H0, u=u, rho=np.ones(N))
+            sim.step(6)
+            out.append(sim.pre())
+        if same:
+            np.testing.assert_array_equal(out[0][1], out[1][1])
+            np.testing.assert_array_equal(out[0][0], out[1][0])
+        else:
+            assert np.abs(out[0][1] - out[1][1]).max() > 1e-6
+            assert np.abs(out[0][0] - out[1][0]).max() > 1e-6
 
 
 def test_energy_balance_of_wall_links(oracle):
