@@ -80,9 +80,10 @@ def test_gradient_matches_oracle_adjoint(L, oracle):
 def test_c5_gradient_vs_central_differences(L):
     """512^2, 2000 steps, u = (0.03, 0), source ~ N(0, 0.01^2): the FP32 adjoint
     gradient (checkpoints every 45 steps, with and without replay) matches FP64
-    central differences (eps = 1e-3) on 16 random nodes within 1e-4 relative L2
-    over the nodes (the per-node relative error is ill-conditioned where a
-    gradient is near zero; it is reported, and bounded at 1e-3)."""
+    central differences (eps = 1e-3) on 16 random nodes: at every node within
+    1e-4 of the largest |dJ/dQ| of the sample, and within 1e-4 relative at
+    every node whose |dJ/dQ| is at least a tenth of that largest value (the
+    relative error of a near-zero gradient measures only its cancellation)."""
     import torch
     from paper_2203_01316_amd.adjoint import source_objective
     n1, T, k = 512, 2000, 0.01
@@ -118,10 +119,15 @@ def test_c5_gradient_vs_central_differences(L):
         fd.append((J64(qp) - J64(qm)) / (2 * eps))
     fd = np.array(fd)
     adj = grads[0][nodes]
-    assert rel_l2(adj, fd) < 1e-4, (adj, fd)
+    scale = np.abs(fd).max()
     per_node = np.abs(adj - fd) / np.abs(fd)
-    print("C5 gradient vs FD: rel L2 %.2e, max per-node %.2e" % (rel_l2(adj, fd), per_node.max()))
-    assert per_node.max() < 1e-3
+    big = np.abs(fd) >= 0.1 * scale
+    print("C5 gradient vs FD: rel L2 %.2e, max |adj - fd| / max |fd| %.2e, max relative on %d nodes %.2e, "
+          "max relative on all %.2e" % (rel_l2(adj, fd), np.abs(adj - fd).max() / scale, big.sum(),
+                                        per_node[big].max(), per_node.max()))
+    assert np.abs(adj - fd).max() < 1e-4 * scale, (adj, fd)
+    assert per_node[big].max() < 1e-4, (adj, fd)
+    assert big.sum() >= 8
 
 
 def _walls(W, case):
@@ -131,6 +137,14 @@ def _walls(W, case):
     elif case == "mix":
         dims = (33, 40, 1)
         flags, q, groups, u, _, _ = W.boundary_mix()
+    elif case == "gap":
+        dims = (20, 16, 1)
+        flags, q_lo, q_hi, groups = W.gap_box(*dims[:2], H_w=2.0)
+        q = np.where(np.random.default_rng(9).uniform(size=q_lo.shape) < 0.5, q_lo, q_hi)
+        u = np.zeros((3, int(np.prod(dims))))
+        u[0] = 0.03
+        u[1] = -0.01
+        u[:, (flags & 15) == W.SOLID] = 0.0
     else:
         dims = (8, 7, 6)
         flags, q, groups = W.sphere_box(*dims, (3.6, 3.3, 2.8), 1.7, inlet=case == "sphere_io")
@@ -143,12 +157,14 @@ def _walls(W, case):
 @pytest.mark.parametrize("case,storage,tol", [("walled", "fp64", 1e-12), ("walled", "fp32", 1e-5),
                                               ("mix", "fp64", 1e-12), ("mix", "fp32", 1e-5),
                                               ("sphere", "fp64", 1e-12), ("sphere_io", "fp64", 1e-12),
-                                              ("sphere_io", "fp32", 1e-5)])
+                                              ("sphere_io", "fp32", 1e-5), ("gap", "fp64", 1e-12),
+                                              ("gap", "fp32", 1e-5)])
 def test_adjoint_step_with_walls_matches_oracle(L, oracle, case, storage, tol):
     """Walls (ABB and IABB on a disc, IABB on a sphere), EQ nodes with and
     without cut links, bulk-handled and listed outlets (the mixed inlet and
-    outlet geometry, the sphere with an inlet and an outlet plane): one GPU
-    adjoint step against the oracle's transpose of its own forward step."""
+    outlet geometry, the sphere with an inlet and an outlet plane), one-node
+    gaps with wall distances below and above 1/2: one GPU adjoint step against
+    the oracle's transpose of its own forward step."""
     import torch
     from paper_2203_01316_amd import workloads as W
     dims, flags, q, groups, u = _walls(W, case)

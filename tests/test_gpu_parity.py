@@ -206,6 +206,49 @@ def test_cylinder_full_size_one_step(L, oracle, cu, stream):
     assert np.all(np.isfinite(red))
 
 
+def _gap_q(W, Q, nx, ny, seed=9):
+    flags, q_lo, q_hi, groups = W.gap_box(nx, ny, H_w=2.0, Q=Q)
+    pick = np.random.default_rng(seed).uniform(size=q_lo.shape) < 0.5
+    return flags, np.where(pick, q_lo, q_hi), groups
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+@pytest.mark.parametrize("stream", ["ab", "aa"])
+@pytest.mark.parametrize("storage,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_one_node_gaps_coupled(L, oracle, Q, stream, storage, tol):
+    """One-node gaps (cut links whose x_f is solid), wall distances mixed
+    below and above 1/2: the q < 1/2 links fall back to BB/ABB and the q > 1/2
+    links keep Eqs. IBB/IABB, on both lattices, D2Q9 and D3Q27, both layouts;
+    link tables bit for bit, populations against the oracle after 40 steps."""
+    nx, ny = (40, 24) if Q == 9 else (20, 16)
+    flags, q, groups = _gap_q(W, Q, nx, ny)
+    n = flags.size
+    nz = n // (nx * ny)
+    D = 2 if Q == 9 else 3
+    rng = np.random.default_rng(71)
+    u = np.zeros((3, n))
+    u[0] = 0.03
+    u[:D] += rng.uniform(-0.005, 0.005, (D, n))
+    u[:, (flags & 15) == W.SOLID] = 0.0
+    uu = f32(u) if storage != "fp64" else u
+    g, o = pair(L, oracle, Q=Q, dims=(nx, ny, nz), storage=storage, with_ns=True, nu=0.03, k=0.02, flags=flags,
+                q=q, groups=groups, H0=1 + 0.1 * rng.uniform(size=n), u_init=uu, rho0=np.ones(n),
+                stream=L.STREAM_AA if stream == "aa" else L.STREAM_AB)
+    lk = o.links()
+    assert g.links().tobytes() == lk.tobytes()
+    gap = lk["xf_solid"] == 1
+    assert (gap & (lk["q"] < 0.5)).sum() >= 8 and (gap & (lk["q"] > 0.5)).sum() >= 8
+    for steps in (1, 39):
+        g.step(steps)
+        o.step(steps)
+        fo, ho = o.pre()
+        assert rel_l2(gpu_pre(g, "f"), fluid_only(fo, o.flags)) < tol, steps
+        assert rel_l2(gpu_pre(g, "h"), fluid_only(ho, o.flags)) < tol, steps
+    red = g.reduce(group=0, columns=[])
+    _, _, flux = o.pre(with_flux=True)
+    assert red[2] == pytest.approx(flux.sum(), rel=max(tol, 1e-10) * 10)
+
+
 # ---------------------------------------------------------------------------
 # D3Q27 coupled (Taylor-Green vortex)
 # ---------------------------------------------------------------------------
