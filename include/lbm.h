@@ -261,6 +261,23 @@ lbm_status lbm_set_populations(lbm_ctx *ctx, int32_t lattice, const double *src_
 lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32_t n_columns,
                       double *out, int32_t nout);
 
+/* Nusselt number of a heated body (Sec. 4.4: Nu = varsigma D / k with
+ * varsigma = qdot / (pi D (T_wall - T_in)); heat fluxes of Eqs.
+ * heat_flux_thorough_heater and heat_flux_section), in FP64 from the
+ * reductions of lbm_reduce() (synchronises).  group: the heater's group;
+ * x_in, x_out: the upstream and downstream section columns; k is the
+ * context's conductivity.  Per unit depth (a D3Q27 lattice with nz layers
+ * divides by nz).  out[5]:
+ *   out[0] = Nu = qdot / (pi k (T_wall - T_in) nz),
+ *            qdot = (q_s + q_out - q_in) / 2 (heater flux and the energy the
+ *            flow gains between the sections, averaged; equal when steady),
+ *   out[1] = Nu from the heater flux alone, q_s / (pi k (T_wall - T_in) nz),
+ *   out[2] = q_s, out[3] = q_in, out[4] = q_out (as out[2..4] of lbm_reduce).
+ * Returns LBM_EINVAL for nout < 5, k <= 0, T_wall == T_in or a column outside
+ * [0, nx), and LBM_EDIVERGED as lbm_reduce() does. */
+lbm_status lbm_nusselt(lbm_ctx *ctx, int32_t group, int32_t x_in, int32_t x_out, double T_wall, double T_in,
+                       double *out, int32_t nout);
+
 /* ---- discrete adjoint ----------------------------------------------------
  * Reverse mode of the advection-diffusion step with a source Q (App. D) for
  * contexts with with_ns = 0 and the central-moment collision of h, periodic

@@ -33,6 +33,9 @@
  *     moment, with the equilibrium evaluated at H = sum(h) + Q/2 (App. D).
  */
 #include <math.h>
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -863,6 +866,66 @@ double ora_section_flux(const ora_cfg *c, const double *h, int X) {
       for (int a = 0; a < c->Q; a++) s += L.e[a][0] * h[a * N + n];
     }
   return s;
+}
+
+/* Nusselt number of a heated body (Sec. 4.4, Eqs. heat_flux_thorough_heater,
+ * heat_flux_section and the Nu definition that follows them) from the post-
+ * collision state (fs, hs) of step t-1: the canonical state at t is streamed
+ * from it, with the energy each wall link injects.
+ *   q_s   = sum over the cut links into group `group` of h_opp(x_b, t) - h*_i(x_b, t-1)
+ *   q_in  = section flux of column x_in, q_out = that of column x_out
+ *   qdot  = (q_s + q_out - q_in) / 2  (heater and the flow's gain, averaged)
+ *   Nu    = qdot / (pi k (T_w - T_in) nz)   (Nu = varsigma D / k with
+ *           varsigma = qdot / (pi D (T_w - T_in)) per unit depth; nz layers)
+ * out: Nu, Nu from q_s alone, q_s, q_in, q_out.  Returns 0, or -1 on bad input. */
+int ora_nusselt(const ora_cfg *c, const double *fs, const double *hs, int group, int x_in, int x_out,
+                double k, double T_w, double T_in, double *out) {
+  long N, nl;
+  int Q = c->Q;
+  double *f = NULL, *h = NULL, *flux = NULL;
+  ora_link *links = NULL;
+  double qs = 0.0, qin, qout, depth;
+  if (check_cfg(c) || x_in < 0 || x_in >= c->nx || x_out < 0 || x_out >= c->nx) return -1;
+  if (!(k > 0.0) || T_w == T_in) return -1;
+  N = nnodes(c);
+  nl = ora_links(c, NULL, 0);
+  if (nl < 0) return -1;
+  f = (double *)malloc(sizeof(double) * Q * N);
+  h = (double *)malloc(sizeof(double) * Q * N);
+  flux = (double *)malloc(sizeof(double) * (nl > 0 ? nl : 1));
+  links = (ora_link *)malloc(sizeof(ora_link) * (nl > 0 ? nl : 1));
+  if (!f || !h || !flux || !links) {
+    free(f);
+    free(h);
+    free(flux);
+    free(links);
+    return -1;
+  }
+  memcpy(h, hs, sizeof(double) * Q * N);
+  if (c->with_ns) memcpy(f, fs, sizeof(double) * Q * N);
+  if (ora_stream(c, fs, hs, f, h, flux) != 0) {
+    free(f);
+    free(h);
+    free(flux);
+    free(links);
+    return -1;
+  }
+  ora_links(c, links, nl);
+  for (long l = 0; l < nl; l++)
+    if (links[l].group == group) qs += flux[l];
+  qin = ora_section_flux(c, h, x_in);
+  qout = ora_section_flux(c, h, x_out);
+  depth = (double)c->nz;
+  out[0] = 0.5 * (qs + qout - qin) / (M_PI * k * (T_w - T_in) * depth);
+  out[1] = qs / (M_PI * k * (T_w - T_in) * depth);
+  out[2] = qs;
+  out[3] = qin;
+  out[4] = qout;
+  free(f);
+  free(h);
+  free(flux);
+  free(links);
+  return 0;
 }
 
 /* ---------------------------------------------------------------------------

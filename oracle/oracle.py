@@ -400,6 +400,14 @@ class Sim:
             lam = self.adjoint_step_dense(lam, dJdQ) if dense else self.adjoint_step(lam, dJdQ)
         return J, dJdQ
 
+    def nusselt(self, group, x_in, x_out, k, T_wall, T_in):
+        """(Nu, Nu from the heater flux alone, q_surface, q_in, q_out) of the
+        canonical state at the current time (Sec. 4.4)."""
+        out = np.zeros(5)
+        assert lib().ora_nusselt(C.byref(self.cfg), _p(self.post_f), _p(self.post_h), int(group), int(x_in),
+                                 int(x_out), C.c_double(k), C.c_double(T_wall), C.c_double(T_in), _p(out)) == 0
+        return tuple(float(v) for v in out)
+
     def section_flux(self, X, h=None):
         if h is None:
             _, h = self.pre()

@@ -952,6 +952,37 @@ lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32
   return LBM_OK;
 }
 
+lbm_status lbm_nusselt(lbm_ctx *ctx, int32_t group, int32_t x_in, int32_t x_out, double T_wall, double T_in,
+                       double *out, int32_t nout) {
+  CTX_CHECK(ctx);
+  if (!out || nout < 5) {
+    set_err(&ctx->err, "out needs at least 5 entries");
+    return LBM_EINVAL;
+  }
+  if (!(ctx->p.k > 0.0) || !std::isfinite(ctx->p.k)) {
+    set_err(&ctx->err, "the context's conductivity k = %g must be finite and > 0", ctx->p.k);
+    return LBM_EINVAL;
+  }
+  if (!std::isfinite(T_wall) || !std::isfinite(T_in) || T_wall == T_in) {
+    set_err(&ctx->err, "T_wall (%g) and T_in (%g) must be finite and differ", T_wall, T_in);
+    return LBM_EINVAL;
+  }
+  const int32_t cols[2] = {x_in, x_out};
+  double red[5];
+  if (lbm_status st = lbm_reduce(ctx, group, cols, 2, red, 5)) return st;
+  // Sec. 4.4: Nu = varsigma D / k with varsigma = qdot / (pi D (T_wall - T_in))
+  // per unit depth (nz layers), qdot the mean of the heater flux and the
+  // energy the flow gains between the two sections
+  const double q_s = red[2], q_in = red[3], q_out = red[4];
+  const double scale = M_PI * ctx->p.k * (T_wall - T_in) * (double)ctx->p.nz;
+  out[0] = 0.5 * (q_s + q_out - q_in) / scale;
+  out[1] = q_s / scale;
+  out[2] = q_s;
+  out[3] = q_in;
+  out[4] = q_out;
+  return LBM_OK;
+}
+
 static lbm_status need_adjoint(lbm_ctx *ctx) {
   if (ctx->p.with_ns || (ctx->p.cumulant & 1)) {
     set_err(&ctx->err, "the adjoint is built for advection-only contexts with the central-moment collision");

@@ -79,6 +79,7 @@ _sig = {
     "lbm_get_populations": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp]),
     "lbm_set_populations": (C.c_int, [_vp, C.c_int32, _vp, C.c_int64]),
     "lbm_reduce": (C.c_int, [_vp, C.c_int32, _vp, C.c_int32, _vp, C.c_int32]),
+    "lbm_nusselt": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double, _vp, C.c_int32]),
     "lbm_state_bytes": (C.c_size_t, [_vp]),
     "lbm_save_state": (C.c_int, [_vp, _vp]),
     "lbm_load_state": (C.c_int, [_vp, _vp]),
@@ -199,19 +200,6 @@ def _groups_struct(groups):
             arr[i].u_w[d] = float(uw[d]) if d < len(uw) else 0.0
         arr[i].H_w = float(g.get("H_w", 0.0))
     return arr
-
-
-def nusselt(q_surface: float, q_in: float, q_out: float, k: float, T_wall: float, T_in: float) -> float:
-    """Nusselt number of a heated cylinder from the FP64 reductions of
-    lbm_reduce (Sec. 4.4): Nu = varsigma D / k with varsigma = qdot / (pi D
-    (T_wall - T_in)), so Nu = qdot / (pi k (T_wall - T_in)).  qdot is the mean
-    of the heater flux (energy the wall links inject per step) and the energy
-    the flow gains between the upstream and the downstream section, q_out -
-    q_in (section fluxes sum e_x h, positive downstream); in a steady state the
-    two agree."""
-    import math
-    qdot = 0.5 * (q_surface + (q_out - q_in))
-    return qdot / (math.pi * k * (T_wall - T_in))
 
 
 class LBM:
@@ -344,6 +332,14 @@ class LBM:
         self._ck(_lib.lbm_reduce(self.ctx, int(group), cols.ctypes.data if len(cols) else None, len(cols),
                                  out.ctypes.data, len(out)))
         return out
+
+    def nusselt(self, group, x_in, x_out, T_wall, T_in):
+        """lbm_nusselt: (Nu, Nu from the heater flux alone, q_surface, q_in,
+        q_out) of the canonical state at the current time."""
+        out = np.zeros(5)
+        self._ck(_lib.lbm_nusselt(self.ctx, int(group), int(x_in), int(x_out), float(T_wall), float(T_in),
+                                  out.ctypes.data, 5))
+        return tuple(float(v) for v in out)
 
     def profile_begin(self, max_steps):
         """Time the bulk and boundary kernels of the next max_steps steps."""

@@ -505,18 +505,25 @@ def test_fp16_dev_gaussian_hill(L):
     assert rel_l2(H.cpu().numpy(), ana) < 3e-3
 
 
-def test_nusselt_from_reductions(L, oracle):
-    """Nu of the coupled cylinder from the FP64 reductions equals the value
-    from the oracle's fluxes (Sec. 4.4 definition)."""
-    g, o = _cylinder(L, oracle, 192, 96, 9.5, "fp64")
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-11), ("fp32", 1e-5)])
+def test_nusselt_against_oracle(L, oracle, storage, tol):
+    """Nu of the coupled cylinder from lbm_nusselt (FP64 reductions and the
+    Sec. 4.4 definition inside the library) against the oracle's own Nu from
+    its wall-link and section fluxes, after 300 steps; every output of the
+    call, and its argument checks."""
+    g, o = _cylinder(L, oracle, 192, 96, 9.5, storage)
     g.step(300)
     o.step(300)
-    red = g.reduce(group=1, columns=[20, 150])
-    _, ho, flux = o.pre(with_flux=True)
-    lk = o.links()
-    nu_g = L.nusselt(red[2], red[3], red[4], 0.06, 11.0, 10.0)
-    nu_o = L.nusselt(flux[lk["group"] == 1].sum(), o.section_flux(20, ho), o.section_flux(150, ho), 0.06, 11.0, 10.0)
-    assert np.isfinite(nu_g) and nu_g == pytest.approx(nu_o, rel=1e-9)
+    got = g.nusselt(1, 20, 150, 11.0, 10.0)
+    ref = oracle_nu = o.nusselt(1, 20, 150, 0.06, 11.0, 10.0)
+    print("Nu GPU", got, "oracle", oracle_nu)
+    assert np.all(np.isfinite(got)) and got[0] > 0
+    for a, b in zip(got, ref):
+        assert a == pytest.approx(b, rel=tol * 10, abs=1e-12)
+    for bad in ((1, 20, 150, 10.0, 10.0), (1, -1, 150, 11.0, 10.0), (1, 20, 192, 11.0, 10.0)):
+        with pytest.raises(L.LBMError) as e:
+            g.nusselt(*bad)
+        assert e.value.status == L.EINVAL
 
 
 def test_confined_cylinder_nusselt(L):
@@ -530,9 +537,8 @@ def test_confined_cylinder_nusselt(L):
     g.set_velocity(f32(u))
     g.init(H0, u=u, rho=rho0)
     g.step(int(5 * info["nx"] / info["U"]))
-    red = g.reduce(group=1, columns=list(info["sections"]))
-    bal = (red[4] - red[3]) / red[2]
-    nu = L.nusselt(red[2], red[3], red[4], info["k"], info["T_cyl"], info["T_in"])
+    nu, _, q_s, q_in, q_out = g.nusselt(1, *info["sections"], info["T_cyl"], info["T_in"])
+    bal = (q_out - q_in) / q_s
     print("confined cylinder Pr = 10: Nu %.3f, heater/section balance %.4f" % (nu, bal))
     assert abs(bal - 1.0) < 0.015
     assert abs(nu - 4.82) < 0.03 * 4.82

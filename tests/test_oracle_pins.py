@@ -373,6 +373,49 @@ def test_concentric_cylinders_bc_order(oracle):
     assert _concentric_error(oracle, 16, "iabb") < 5e-4
 
 
+def test_heater_flux_concentric_closed_form(oracle):
+    """Sec. 4.3/4.4: steady conduction between concentric cylinders r_i = R/2,
+    r_o = R carries the heat 2 pi k (T_i - T_o) / ln(r_o / r_i) per unit depth,
+    so the Nusselt number from the inner wall's link flux (Eq.
+    heat_flux_thorough_heater; Nu = qdot / (pi k dT)) is 2 / ln 2.  It
+    converges at second order (R = 8, 16, 32); the outer wall removes the same
+    heat."""
+    errs = []
+    for R in (8, 16, 32):
+        L, flags, q, (Ti, To), T, fluid = W.concentric_cylinders(R)
+        k = 0.1
+        sim = oracle.Sim(9, L, L, s_h=oracle.preset(9, "trt", oracle.s_main(k)), flags=flags, qlink=q,
+                         groups=[dict(h_scheme=oracle.IABB, H_w=Ti), dict(h_scheme=oracle.IABB, H_w=To)])
+        sim.init(T)
+        sim.step(3 * R * R)
+        nu_in = sim.nusselt(0, 0, 0, k, Ti, To)
+        nu_out = sim.nusselt(1, 0, 0, k, Ti, To)
+        assert nu_out[2] == pytest.approx(-nu_in[2], rel=1e-6)
+        errs.append(nu_in[1] / (2.0 / math.log(2.0)) - 1.0)
+    assert abs(errs[2]) < 1e-4, errs
+    assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0, errs
+
+
+def test_nusselt_definition_on_outputs(oracle):
+    """The oracle's Nu combines its own heater flux and section fluxes as
+    Sec. 4.4 defines them: qdot = (q_s + q_out - q_in) / 2, Nu = qdot / (pi k
+    (T_w - T_in)); checked against the link fluxes and section fluxes of the
+    same state on the heated-cylinder inputs."""
+    flags, q, groups, u, rho0, H0 = W.heated_cylinder(64, 32, 4.5, u_in=0.04, amp=1e-3, seed=0)
+    sim = oracle.Sim(9, 64, 32, with_ns=True, s_f=oracle.preset(9, "ns", oracle.s_main(0.04)),
+                     s_h=oracle.preset(9, "trt", oracle.s_main(0.06)), uvel=u, flags=flags, qlink=q, groups=groups)
+    sim.init(H0, u=u, rho=rho0)
+    sim.step(40)
+    nu, nu_s, q_s, q_in, q_out = sim.nusselt(1, 6, 50, 0.06, 11.0, 10.0)
+    _, h, flux = sim.pre(with_flux=True)
+    lk = sim.links()
+    assert q_s == pytest.approx(flux[lk["group"] == 1].sum(), rel=1e-13)
+    assert q_in == sim.section_flux(6, h) and q_out == sim.section_flux(50, h)
+    assert nu == pytest.approx(0.5 * (q_s + q_out - q_in) / (math.pi * 0.06), rel=1e-14)
+    assert nu_s == pytest.approx(q_s / (math.pi * 0.06), rel=1e-14)
+    assert q_s > 0
+
+
 def test_shear_wave_decay_gives_viscosity(oracle):
     """f lattice, CM with second-order moments at s_nu = 1/(3 nu + 1/2): a shear
     wave u_x = A sin(2 pi y / L) decays as exp(-nu k^2 t)."""
