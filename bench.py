@@ -257,7 +257,7 @@ def cpu_baseline(inputs, steps, single_thread=True):
     flags, q, groups, u, rho0, H0, nx, ny, nu, k = inputs
     sf = O.preset(9, "ns", O.s_main(nu))
     sh = O.preset(9, "trt", O.s_main(k))
-    o = O.Sim(9, nx, ny, with_ns=True, s_f=sf, s_h=sh, uvel=u, flags=flags, qlink=q, groups=groups)
+    o = O.Sim(9, nx, ny, with_ns=True, s_f=sf, s_h=sh, uvel=u, flags=flags, qlink=q, groups=groups, s_bulk_f=1.0)
     o.init(H0, u=u, rho=rho0)
     t0 = time.perf_counter()
     o.step(steps)

@@ -79,7 +79,8 @@ typedef enum { LBM_STREAM_AB = 0, LBM_STREAM_AA = 1 } lbm_stream_mode;
  *  LBM_CM_1ST : first-order moments at s^H, all others at 1;
  *  LBM_CM_TRT : moments of odd total order at s^H, even ones at 1
  *               (the paper's recommended kernel for h);
- *  LBM_CM_NS  : second-order moments at s_nu, all others at 1 (f lattice);
+ *  LBM_CM_NS  : second-order moments at s_nu, all others at 1 (f lattice),
+ *               with the trace of the diagonal block at s_bulk_f (default 1);
  *  LBM_CM_CUSTOM : rates taken from s_custom_f / s_custom_h. */
 typedef enum {
   LBM_CM_SRT = 0,
@@ -142,6 +143,17 @@ typedef struct {
   double u0[3];     /* uniform advection velocity (u_mode 0) */
   double s_custom_f[27]; /* per-moment rates, LBM_CM_CUSTOM */
   double s_custom_h[27];
+  double s_bulk_f;  /* rate of the trace of f's diagonal second-order block
+                     * (central moments 200 + 020 + 002, or the cumulants of
+                     * the same indices): the bulk viscosity.  The deviatoric
+                     * parts (differences of those moments) keep the diagonal
+                     * rate of 200, i.e. s_nu under LBM_CM_NS.  0 selects 1 for
+                     * LBM_CM_NS (the separate bulk rate of the cumulant f
+                     * kernel of Geier et al. 2015, which the paper adopts)
+                     * and no separate trace rate otherwise; a value in
+                     * (0, 2) sets it (with LBM_CM_CUSTOM the custom rates of
+                     * 200, 020 and 002 must then be equal).  Setting it to
+                     * s_nu reproduces the diagonal relaxation. */
 } lbm_params;
 
 /* One cut link (Sec. 3): boundary node x_b, direction dir from x_b towards the
@@ -169,8 +181,10 @@ const char *lbm_version(void);
 size_t lbm_workspace_bytes(const lbm_params *p);
 
 /* Per-moment relaxation rates the library uses for p, in the moment order
- * above: s_f[27] and s_h[27] (entries past Q are 1). */
-lbm_status lbm_relaxation_rates(const lbm_params *p, double *s_f, double *s_h);
+ * above: s_f[27] and s_h[27] (entries past Q are 1), and *s_bulk_f the rate
+ * of the trace of f's second-order block (0: none, the trace relaxes with
+ * the diagonal rates).  Any output may be NULL. */
+lbm_status lbm_relaxation_rates(const lbm_params *p, double *s_f, double *s_h, double *s_bulk_f);
 
 /* Counts the cut links and the boundary-node records of a geometry (flags as
  * in lbm_set_geometry), the capacities max_links and max_special must hold.

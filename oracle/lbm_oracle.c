@@ -265,6 +265,13 @@ typedef struct {
   double Minv[ORA_MAXQ * ORA_MAXQ];
 } ora_ctx;
 
+/* Position of the moment with multi-index n in the lattice's moment order. */
+static int mom_slot(const ora_lat *L, const int n[3]) {
+  for (int k = 0; k < L->Q; k++)
+    if (L->mo[k][0] == n[0] && L->mo[k][1] == n[1] && L->mo[k][2] == n[2]) return k;
+  return -1;
+}
+
 static int ctx_init(int Q, ora_ctx *C) {
   if (build_lattice(Q, &C->L)) return -1;
   return ora_matrix_Minv(Q, C->Minv);
@@ -309,14 +316,60 @@ int ora_cm_equilibrium(int Q, double psi, double *eq) {
   return 0;
 }
 
+/* Relaxation of a moment (or cumulant) vector v toward its equilibrium veq
+ * with the diagonal rates s.  With s_bulk > 0 the second-order diagonal block
+ * (200, 020, 002; 20, 02 in two dimensions) is relaxed in the basis of its
+ * trace and its deviatoric parts instead: the trace t = sum_d v_dd at
+ * s_bulk, the differences v_xx - v_dd (d != x) at s of 200, which must equal
+ * those of 020 and 002.  The trace carries the bulk viscosity, the deviator
+ * the shear viscosity (Geier et al. 2015, whose hydrodynamic kernel the paper
+ * adopts, relaxes the two with separate rates). */
+static void relax_moments(const ora_lat *L, double *v, const double *veq, const double *s, double s_bulk) {
+  int Q = L->Q, D = Q == 27 ? 3 : 2;
+  int dia[3] = {-1, -1, -1};
+  double pre[ORA_MAXQ];
+  for (int k = 0; k < Q; k++) {
+    pre[k] = v[k];
+    v[k] = v[k] + s[k] * (veq[k] - v[k]);
+  }
+  if (!(s_bulk > 0.0)) return;
+  for (int d = 0; d < D; d++) {
+    int n[3] = {0, 0, 0};
+    n[d] = 2;
+    dia[d] = mom_slot(L, n);
+  }
+  {
+    double t = 0.0, teq = 0.0, dev[3], deveq[3], tpost, devpost[3];
+    for (int d = 0; d < D; d++) {
+      t += pre[dia[d]];
+      teq += veq[dia[d]];
+    }
+    for (int d = 1; d < D; d++) {
+      dev[d] = pre[dia[0]] - pre[dia[d]];
+      deveq[d] = veq[dia[0]] - veq[dia[d]];
+    }
+    tpost = t + s_bulk * (teq - t);
+    for (int d = 1; d < D; d++) devpost[d] = dev[d] + s[dia[0]] * (deveq[d] - dev[d]);
+    /* invert t = v_x + sum_d v_d, dev_d = v_x - v_d:  D v_x = t + sum_d dev_d */
+    {
+      double vx = tpost;
+      for (int d = 1; d < D; d++) vx += devpost[d];
+      vx /= (double)D;
+      v[dia[0]] = vx;
+      for (int d = 1; d < D; d++) v[dia[d]] = vx - devpost[d];
+    }
+  }
+}
+
 /* One central-moment collision (Eq. H_cm_collision, relaxation of Sec. 2.1.1,
  * source of App. D carried over to central moments):
  *   Y~  = T(u) g
  *   psi = Y~_000 + src/2
  *   Y~* = Y~ + S (Y~eq(psi) - Y~) + (1 - s_000/2) src e_000
- *   g*  = M^-1 N(-u) Y~*                                                     */
+ *   g*  = M^-1 N(-u) Y~*
+ * (S with the trace split of relax_moments when s_bulk > 0).               */
 static void collide_node(const ora_ctx *C, const double *g, const double u[3],
-                         const double *s, double src, double *gs) {
+                         const double *s, double s_bulk, double src, double *gs) {
   int Q = C->L.Q;
   double T[ORA_MAXQ * ORA_MAXQ], cm[ORA_MAXQ], eq[ORA_MAXQ];
   matrix_T(&C->L, u, T);
@@ -326,16 +379,16 @@ static void collide_node(const ora_ctx *C, const double *g, const double u[3],
     cm[k] = v;
   }
   cm_equilibrium(&C->L, cm[0] + 0.5 * src, eq);
-  for (int k = 0; k < Q; k++) cm[k] = cm[k] + s[k] * (eq[k] - cm[k]);
+  relax_moments(&C->L, cm, eq, s, s_bulk);
   cm[0] += (1.0 - 0.5 * s[0]) * src;
   from_central(C, u, cm, gs);
 }
 
 int ora_collide_node(int Q, const double *g, const double *u, const double *s,
-                     double src, double *gs) {
+                     double src, double s_bulk, double *gs) {
   ora_ctx C;
   if (ctx_init(Q, &C)) return -1;
-  collide_node(&C, g, u, s, src, gs);
+  collide_node(&C, g, u, s, s_bulk, src, gs);
   return 0;
 }
 
@@ -354,11 +407,6 @@ int ora_collide_node(int Q, const double *g, const double *u, const double *s,
  * inside the moment set, so the 27 (9) cumulants are exactly those of the
  * lattice's moments.
  * ------------------------------------------------------------------------- */
-static int mom_slot(const ora_lat *L, const int n[3]) {
-  for (int k = 0; k < L->Q; k++)
-    if (L->mo[k][0] == n[0] && L->mo[k][1] == n[1] && L->mo[k][2] == n[2]) return k;
-  return -1;
-}
 
 static int mom_order(const ora_lat *L, int k) { return L->mo[k][0] + L->mo[k][1] + L->mo[k][2]; }
 
@@ -450,13 +498,12 @@ static void cu_equilibrium(const ora_lat *L, double psi, const double u[3], doub
  *   C   = cumulants(g),  psi = C_000 + src/2,
  *   C*  = C + S (C^eq(psi, u) - C) + (1 - s_000/2) src e_000,
  *   g*  = cumulants^-1(C*).                                                 */
-static void collide_node_cu(const ora_ctx *C, const double *g, const double u[3], const double *s, double src,
-                            double *gs) {
-  int Q = C->L.Q;
+static void collide_node_cu(const ora_ctx *C, const double *g, const double u[3], const double *s, double s_bulk,
+                            double src, double *gs) {
   double c[ORA_MAXQ], eq[ORA_MAXQ];
   cumulants(&C->L, g, c);
   cu_equilibrium(&C->L, c[0] + 0.5 * src, u, eq);
-  for (int k = 0; k < Q; k++) c[k] = c[k] + s[k] * (eq[k] - c[k]);
+  relax_moments(&C->L, c, eq, s, s_bulk);
   c[0] += (1.0 - 0.5 * s[0]) * src;
   from_cumulants(C, c, gs);
 }
@@ -475,10 +522,11 @@ int ora_from_cumulants(int Q, const double *c, double *g) {
   return 0;
 }
 
-int ora_collide_node_cu(int Q, const double *g, const double *u, const double *s, double src, double *gs) {
+int ora_collide_node_cu(int Q, const double *g, const double *u, const double *s, double src, double s_bulk,
+                        double *gs) {
   ora_ctx C;
   if (ctx_init(Q, &C)) return -1;
-  collide_node_cu(&C, g, u, s, src, gs);
+  collide_node_cu(&C, g, u, s, s_bulk, src, gs);
   return 0;
 }
 
@@ -514,6 +562,9 @@ typedef struct {
   const ora_group *groups;
   int32_t cu_f;         /* 1: f uses the cumulant collision, 0: central moments */
   int32_t cu_h;         /* the same for h */
+  double s_bulk_f;      /* > 0: trace of the second-order block of f relaxed at
+                         * this rate, its deviator at s_f of 200 (relax_moments);
+                         * 0: the diagonal rates s_f alone */
 } ora_cfg;
 
 typedef struct {
@@ -600,9 +651,9 @@ int ora_collide(const ora_cfg *c, const double *f, const double *h, double *fs, 
       if (c->collide_off)
         memcpy(gs, g, sizeof(double) * Q);
       else if (c->cu_f)
-        collide_node_cu(&C, g, u, c->s_f, 0.0, gs);
+        collide_node_cu(&C, g, u, c->s_f, c->s_bulk_f, 0.0, gs);
       else
-        collide_node(&C, g, u, c->s_f, 0.0, gs);
+        collide_node(&C, g, u, c->s_f, c->s_bulk_f, 0.0, gs);
       for (int a = 0; a < Q; a++) fs[a * N + n] = gs[a];
     } else {
       node_velocity_prescribed(c, n, u);
@@ -611,9 +662,9 @@ int ora_collide(const ora_cfg *c, const double *f, const double *h, double *fs, 
     if (c->collide_off)
       memcpy(gs, g, sizeof(double) * Q);
     else if (c->cu_h)
-      collide_node_cu(&C, g, u, c->s_h, c->src ? c->src[n] : 0.0, gs);
+      collide_node_cu(&C, g, u, c->s_h, 0.0, c->src ? c->src[n] : 0.0, gs);
     else
-      collide_node(&C, g, u, c->s_h, c->src ? c->src[n] : 0.0, gs);
+      collide_node(&C, g, u, c->s_h, 0.0, c->src ? c->src[n] : 0.0, gs);
     for (int a = 0; a < Q; a++) hs[a * N + n] = gs[a];
   }
   return 0;

@@ -48,7 +48,7 @@ class Cfg(C.Structure):
                 ("s_f", C.c_double * 27), ("s_h", C.c_double * 27), ("u0", C.c_double * 3),
                 ("uvel", C.c_void_p), ("src", C.c_void_p), ("flags", C.c_void_p),
                 ("qlink", C.c_void_p), ("n_groups", C.c_int32), ("collide_off", C.c_int32),
-                ("groups", C.c_void_p), ("cu_f", C.c_int32), ("cu_h", C.c_int32)]
+                ("groups", C.c_void_p), ("cu_f", C.c_int32), ("cu_h", C.c_int32), ("s_bulk_f", C.c_double)]
 
 
 class Link(C.Structure):
@@ -121,12 +121,14 @@ def collision_matrix(Q: int, u, s):
     return A, b
 
 
-def collide_node(Q: int, g, u, s, src: float = 0.0):
+def collide_node(Q: int, g, u, s, src: float = 0.0, s_bulk: float = 0.0):
+    """One central-moment collision; s_bulk > 0 relaxes the trace of the
+    second-order block at that rate and its deviator at s[200]."""
     g = np.ascontiguousarray(g, dtype=np.float64)
     uu = np.ascontiguousarray(u, dtype=np.float64)
     ss = np.ascontiguousarray(s, dtype=np.float64)
     out = np.zeros(Q)
-    assert lib().ora_collide_node(Q, _p(g), _p(uu), _p(ss), C.c_double(src), _p(out)) == 0
+    assert lib().ora_collide_node(Q, _p(g), _p(uu), _p(ss), C.c_double(src), C.c_double(s_bulk), _p(out)) == 0
     return out
 
 
@@ -146,12 +148,12 @@ def from_cumulants(Q: int, c):
     return out
 
 
-def collide_node_cu(Q: int, g, u, s, src: float = 0.0):
+def collide_node_cu(Q: int, g, u, s, src: float = 0.0, s_bulk: float = 0.0):
     g = np.ascontiguousarray(g, dtype=np.float64)
     uu = np.ascontiguousarray(u, dtype=np.float64)
     ss = np.ascontiguousarray(s, dtype=np.float64)
     out = np.zeros(Q)
-    assert lib().ora_collide_node_cu(Q, _p(g), _p(uu), _p(ss), C.c_double(src), _p(out)) == 0
+    assert lib().ora_collide_node_cu(Q, _p(g), _p(uu), _p(ss), C.c_double(src), C.c_double(s_bulk), _p(out)) == 0
     return out
 
 
@@ -189,7 +191,7 @@ def preset(Q: int, kind: str, rate: float) -> np.ndarray:
 class Sim:
     def __init__(self, Q, nx, ny, nz=1, *, with_ns=False, s_f=None, s_h=None, u0=(0.0, 0.0, 0.0),
                  uvel=None, src=None, flags=None, qlink=None, groups=(), collide_off=False, cu_f=False,
-                 cu_h=False):
+                 cu_h=False, s_bulk_f=0.0):
         self.Q, self.nx, self.ny, self.nz = Q, nx, ny, nz
         self.N = nx * ny * nz
         self.with_ns = bool(with_ns)
@@ -200,6 +202,7 @@ class Sim:
         c.collide_off = int(collide_off)
         c.cu_f = int(cu_f)
         c.cu_h = int(cu_h)
+        c.s_bulk_f = float(s_bulk_f)
         sf = np.ones(27) if s_f is None else np.asarray(s_f, float)
         sh = np.ones(27) if s_h is None else np.asarray(s_h, float)
         for k in range(27):

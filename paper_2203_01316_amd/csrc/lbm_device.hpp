@@ -261,12 +261,42 @@ __host__ __device__ constexpr R ceq1(int m) {
   return m == 0 ? R(1) : (m == 1 ? R(0) : R(1) / R(3));
 }
 
+// Chimera slots of the diagonal second-order moments 200, 020 (and 002).
+template <int D>
+__host__ __device__ constexpr int diag2(int d) {
+  return D == 2 ? (d == 0 ? 6 : 2) : (d == 0 ? 18 : (d == 1 ? 6 : 2));
+}
+
+// Trace of the diagonal second-order block (central moments or cumulants).
+template <int D, class R>
+__device__ __forceinline__ R trace2(const R *K) {
+  R t = K[diag2<D>(0)] + K[diag2<D>(1)];
+  if constexpr (D == 3) t += K[diag2<D>(2)];
+  return t;
+}
+
+// Separate rate of that trace (bulk viscosity).  After the diagonal
+// relaxation at s of 200 (= 020 = 002), adding db (teq / D - t / D) to each
+// diagonal moment, with t the pre-collision trace, teq its equilibrium and
+// db = s_bulk - s_200, moves the trace at s_bulk and leaves the differences
+// of the diagonal moments (the deviator) as the diagonal rate left them.
+template <int D, class R>
+__device__ __forceinline__ void bulk_shift(R *K, R t_pre, R teq, R db) {
+  const R d = db * (teq - t_pre) * (R(1) / R(D));
+  K[diag2<D>(0)] += d;
+  K[diag2<D>(1)] += d;
+  if constexpr (D == 3) K[diag2<D>(2)] += d;
+}
+
 // Relaxation toward the central-moment equilibrium, in place on the central
 // moments K (chimera order), rates s (chimera order).  psi is the conserved
 // zeroth moment used by the equilibrium; src the source of App. D (0 if none).
-template <int D, class R>
-__device__ __forceinline__ void relax(R *K, const R *s, R psi, R src) {
+// TR: the trace of the second-order block relaxes at s_200 + db.
+template <int D, class R, bool TR = false>
+__device__ __forceinline__ void relax(R *K, const R *s, R psi, R src, R db = R(0)) {
   constexpr int NQ = D == 2 ? 9 : 27;
+  R t_pre = R(0);
+  if constexpr (TR) t_pre = trace2<D, R>(K);
 #pragma unroll
   for (int k = 0; k < NQ; k++) {
     const int m = D == 2 ? k / 3 : k / 9;
@@ -278,16 +308,17 @@ __device__ __forceinline__ void relax(R *K, const R *s, R psi, R src) {
     else
       K[k] = K[k] + s[k] * (psi * c - K[k]);
   }
+  if constexpr (TR) bulk_shift<D, R>(K, t_pre, psi * (R(D) / R(3)), db);
   K[0] += (R(1) - R(0.5) * s[0]) * src;
 }
 
 // Full central-moment collision of one lattice (chimera slots in, chimera
 // slots out): g* = T(u)^-1 [Y~ + S (Y~eq - Y~)].
-template <int D, class R>
-__device__ __forceinline__ void collide(R *g, const R *s, R ux, R uy, R uz, R src) {
+template <int D, class R, bool TR = false>
+__device__ __forceinline__ void collide(R *g, const R *s, R ux, R uy, R uz, R src, R db = R(0)) {
   to_central<D, R>(g, ux, uy, uz);
   const R psi = g[0] + R(0.5) * src;
-  relax<D, R>(g, s, psi, src);
+  relax<D, R, TR>(g, s, psi, src, db);
   from_central<D, R>(g, ux, uy, uz);
 }
 
@@ -368,9 +399,10 @@ __device__ __forceinline__ void cumulant_recursion(R *mu, R *c) {
 }
 
 // K > 0: the rates of every cumulant above order K are 1 (the caller checks),
-// which those cumulants then reach exactly; K = 0: no assumption.
-template <int D, class R, int K = 0>
-__device__ __forceinline__ void collide_cu(R *g, const R *s, R ux, R uy, R uz, R src) {
+// which those cumulants then reach exactly; K = 0: no assumption.  TR: the
+// trace of the second-order cumulants relaxes at s_200 + db (bulk_shift).
+template <int D, class R, int K = 0, bool TR = false>
+__device__ __forceinline__ void collide_cu(R *g, const R *s, R ux, R uy, R uz, R src, R db = R(0)) {
   constexpr int NQ = D == 2 ? 9 : 27;
   to_central<D, R>(g, ux, uy, uz);
   const R k0 = g[0];
@@ -381,6 +413,8 @@ __device__ __forceinline__ void collide_cu(R *g, const R *s, R ux, R uy, R uz, R
   R c[NQ];
   c[0] = k0;
   cumulant_recursion<D, true, R, K>(g, c);
+  R t_pre = R(0);
+  if constexpr (TR) t_pre = trace2<D, R>(c);
 #pragma unroll
   for (int k = 1; k < NQ; k++) {
     const R eq = cu_pure2<D>(k) ? R(1) / R(3) : R(0);
@@ -389,6 +423,7 @@ __device__ __forceinline__ void collide_cu(R *g, const R *s, R ux, R uy, R uz, R
     else
       c[k] = c[k] + s[k] * (eq - c[k]);
   }
+  if constexpr (TR) bulk_shift<D, R>(c, t_pre, R(D) / R(3), db);
   const R psi = k0 + R(0.5) * src;
   const R c0 = k0 + s[0] * (psi - k0) + (R(1) - R(0.5) * s[0]) * src;
   cumulant_recursion<D, false, R, K>(g, c);

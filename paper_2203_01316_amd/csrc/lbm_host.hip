@@ -111,7 +111,31 @@ bool validate(const lbm_params *p, std::string *err) {
   for (int d = 0; d < 3; d++)
     if (!std::isfinite(p->u0[d])) return set_err(err, "u0[%d] is not finite", d);
   if (!std::isfinite(p->rho_ref) || !std::isfinite(p->H_ref)) return set_err(err, "rho_ref/H_ref not finite");
+  if (!(p->s_bulk_f >= 0.0 && p->s_bulk_f < 2.0))
+    return set_err(err, "s_bulk_f must be 0 (default) or a rate in (0, 2), got %g", p->s_bulk_f);
+  if (p->with_ns && p->s_bulk_f > 0.0 && p->relax_f == LBM_CM_CUSTOM) {
+    // the deviatoric rate is the common rate of the diagonal second-order moments
+    const int Q = p->lattice;
+    double r[3];
+    int nd = 0;
+    for (int k = 0; k < Q; k++) {
+      int m[3];
+      moment_index(Q, k, m);
+      if (m[0] + m[1] + m[2] == 2 && (m[0] == 2 || m[1] == 2 || m[2] == 2)) r[nd++] = p->s_custom_f[k];
+    }
+    for (int d = 1; d < nd; d++)
+      if (r[d] != r[0])
+        return set_err(err, "s_bulk_f > 0 needs equal custom rates of f at the diagonal second-order moments");
+  }
   return true;
+}
+
+// Trace rate of f's second-order block: s_bulk_f, or 1 for the LBM_CM_NS
+// preset when s_bulk_f is 0; 0 (no separate rate) otherwise.
+double bulk_rate(const lbm_params *p) {
+  if (!p->with_ns) return 0.0;
+  if (p->s_bulk_f > 0.0) return p->s_bulk_f;
+  return p->relax_f == LBM_CM_NS ? 1.0 : 0.0;
 }
 
 void preset_rates(const lbm_params *p, int relax, double rate, const double *custom, double *s) {
@@ -533,6 +557,10 @@ static KArgs make_args(lbm_ctx *ctx, int src_copy) {
     a.sf32[k] = (float)ctx->sfc[k];
     a.sh32[k] = (float)ctx->shc[k];
   }
+  // chimera slot 2 is the moment 020 (D2Q9: 02), one of the diagonal ones
+  const double sb = bulk_rate(&ctx->p);
+  a.dbulk_f = sb > 0.0 ? sb - ctx->sfc[2] : 0.0;
+  a.dbulk_f32 = sb > 0.0 ? (float)sb - (float)ctx->sfc[2] : 0.0f;
   for (int d = 0; d < 3; d++) a.u0[d] = ctx->p.u0[d];
   const bool dev = ctx->p.storage == LBM_FP32_DEV || ctx->p.storage == LBM_FP16_DEV;
   a.fref = dev ? ctx->p.rho_ref : 0.0;
@@ -601,12 +629,13 @@ size_t lbm_workspace_bytes(const lbm_params *p) {
   return layout(p).total;
 }
 
-lbm_status lbm_relaxation_rates(const lbm_params *p, double *s_f, double *s_h) {
+lbm_status lbm_relaxation_rates(const lbm_params *p, double *s_f, double *s_h, double *s_bulk_f) {
   if (!validate(p, nullptr)) return LBM_EINVAL;
   double a[27], b[27];
   compute_rates(p, a, b);
   if (s_f) memcpy(s_f, a, sizeof(a));
   if (s_h) memcpy(s_h, b, sizeof(b));
+  if (s_bulk_f) *s_bulk_f = bulk_rate(p);
   return LBM_OK;
 }
 

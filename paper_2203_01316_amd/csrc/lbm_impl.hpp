@@ -189,6 +189,18 @@ template <>
 __device__ __forceinline__ const float *rates<float>(const KArgs &a, bool f) {
   return f ? a.sf32 : a.sh32;
 }
+// Difference between the trace rate of f's second-order block and its
+// diagonal rate (0: the trace relaxes with the deviator).
+template <class R>
+__device__ __forceinline__ R bulk_delta(const KArgs &a);
+template <>
+__device__ __forceinline__ double bulk_delta<double>(const KArgs &a) {
+  return a.dbulk_f;
+}
+template <>
+__device__ __forceinline__ float bulk_delta<float>(const KArgs &a) {
+  return a.dbulk_f32;
+}
 
 __device__ __forceinline__ int wrapm(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
@@ -372,11 +384,11 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
 #pragma unroll
       for (int i = 0; i < Q; i++) g[Lat<Q>::slot(i)] = f[i];
       if constexpr ((CU & 2) && (CU & 4))
-        collide_cu<D, R, 2>(g, rates<R>(a, true), ux, uy, uz, R(0));
+        collide_cu<D, R, 2, true>(g, rates<R>(a, true), ux, uy, uz, R(0), bulk_delta<R>(a));
       else if constexpr (CU & 2)
-        collide_cu<D, R>(g, rates<R>(a, true), ux, uy, uz, R(0));
+        collide_cu<D, R, 0, true>(g, rates<R>(a, true), ux, uy, uz, R(0), bulk_delta<R>(a));
       else
-        collide<D, R>(g, rates<R>(a, true), ux, uy, uz, R(0));
+        collide<D, R, true>(g, rates<R>(a, true), ux, uy, uz, R(0), bulk_delta<R>(a));
 #pragma unroll
       for (int k = 0; k < Q; k++) {
         const int i = split_order<Q, LAY, CU>() ? dir_at_pos<Q>(k) : k;

@@ -109,6 +109,8 @@ struct KArgs {
   double sh[27];           // rates of h, chimera order
   float sf32[27];          // the same rates rounded for FP32 arithmetic
   float sh32[27];
+  double dbulk_f;          // trace rate of f's second-order block minus its
+  float dbulk_f32;         // diagonal rate (0: no separate trace rate)
   double u0[3];
   double fref, href;       // deviation references (0 unless *_DEV storage)
   double *out0, *out1, *out2, *out3;  // MODE_PRE / MODE_MACRO outputs

@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("with_source", C.c_int32), ("max_links", C.c_int32), ("max_special", C.c_int32),
                 ("cumulant", C.c_int32), ("nu", C.c_double), ("k", C.c_double),
                 ("rho_ref", C.c_double), ("H_ref", C.c_double), ("u0", C.c_double * 3),
-                ("s_custom_f", C.c_double * 27), ("s_custom_h", C.c_double * 27)]
+                ("s_custom_f", C.c_double * 27), ("s_custom_h", C.c_double * 27), ("s_bulk_f", C.c_double)]
 
 
 class Group(C.Structure):
@@ -63,7 +63,7 @@ _vp = C.c_void_p
 _sig = {
     "lbm_version": (C.c_char_p, []),
     "lbm_workspace_bytes": (C.c_size_t, [_P(Params)]),
-    "lbm_relaxation_rates": (C.c_int, [_P(Params), _vp, _vp]),
+    "lbm_relaxation_rates": (C.c_int, [_P(Params), _vp, _vp, _vp]),
     "lbm_count_geometry": (C.c_int, [_P(Params), _vp, _P(C.c_int64), _P(C.c_int64)]),
     "lbm_build_links": (C.c_int, [_P(Params), _vp, _vp, C.c_int32, _vp, C.c_int64, _P(C.c_int64)]),
     "lbm_last_error": (C.c_char_p, [_vp]),
@@ -117,9 +117,11 @@ def version() -> str:
 def make_params(lattice=D2Q9, nx=64, ny=64, nz=1, *, with_ns=False, storage="fp64", stream=STREAM_AB,
                 relax_f="ns", relax_h="trt", nu=0.0, k=0.01, u0=(0.0, 0.0, 0.0), u_mode=0,
                 with_source=False, max_links=0, max_special=0, rho_ref=0.0, H_ref=0.0,
-                s_custom_f=None, s_custom_h=None, cumulant_f=False, cumulant_h=False) -> Params:
+                s_custom_f=None, s_custom_h=None, cumulant_f=False, cumulant_h=False, s_bulk_f=0.0) -> Params:
     """Library parameters.  cumulant_f / cumulant_h select the cumulant
-    collision for that lattice (relax_h="1st" is the paper's Cumulants-1st)."""
+    collision for that lattice (relax_h="1st" is the paper's Cumulants-1st);
+    s_bulk_f the trace rate of f's second-order block (0: the library's
+    default, see lbm_params)."""
     p = Params()
     p.lattice, p.nx, p.ny, p.nz = int(lattice), int(nx), int(ny), int(nz)
     p.with_ns = int(bool(with_ns))
@@ -133,6 +135,7 @@ def make_params(lattice=D2Q9, nx=64, ny=64, nz=1, *, with_ns=False, storage="fp6
     p.max_links, p.max_special = int(max_links), int(max_special)
     p.nu, p.k = float(nu), float(k)
     p.rho_ref, p.H_ref = float(rho_ref), float(H_ref)
+    p.s_bulk_f = float(s_bulk_f)
     for d in range(3):
         p.u0[d] = float(u0[d]) if d < len(u0) else 0.0
     for k_ in range(27):
@@ -149,10 +152,18 @@ def workspace_bytes(p: Params) -> int:
 
 
 def relaxation_rates(p: Params):
+    """Per-moment rates (s_f[27], s_h[27]) in the header's moment order."""
     sf = np.zeros(27)
     sh = np.zeros(27)
-    _check(_lib.lbm_relaxation_rates(C.byref(p), sf.ctypes.data, sh.ctypes.data))
+    _check(_lib.lbm_relaxation_rates(C.byref(p), sf.ctypes.data, sh.ctypes.data, None))
     return sf, sh
+
+
+def bulk_rate(p: Params) -> float:
+    """Trace rate of f's second-order block (0: no separate rate)."""
+    sb = C.c_double()
+    _check(_lib.lbm_relaxation_rates(C.byref(p), None, None, C.byref(sb)))
+    return float(sb.value)
 
 
 def _host_flags(flags):

@@ -44,7 +44,7 @@ def pair(L, O, *, Q, dims, storage="fp64", with_ns=False, relax_h="trt", nu=0.0,
         g.set_source(sr)
     sf, sh = L.relaxation_rates(g.params)
     o = O.Sim(Q, nx, ny, nz, with_ns=with_ns, s_f=sf, s_h=sh, u0=u0, uvel=uv, src=sr, flags=flags, qlink=q,
-              groups=list(groups), cu_f=cu_f, cu_h=cu_h)
+              groups=list(groups), cu_f=cu_f, cu_h=cu_h, s_bulk_f=L.bulk_rate(g.params))
     H0 = np.ones(n) if H0 is None else np.asarray(H0, float).reshape(n)
     g.init(H0, u=u_init, rho=rho0)
     if oracle_init:

@@ -72,6 +72,26 @@ def test_presets_match_oracle(L, oracle, Q):
         sf, sh = L.relaxation_rates(p)
         np.testing.assert_array_equal(sh[:Q], oracle.preset(Q, name, oracle.s_main(0.0021))[:Q])
         np.testing.assert_array_equal(sf[:Q], oracle.preset(Q, "ns", oracle.s_main(0.013))[:Q])
+        assert L.bulk_rate(p) == 1.0
+
+
+def test_bulk_rate_choices(L):
+    """s_bulk_f: 0 selects 1 for the hydrodynamic preset and no separate trace
+    rate for the others; an explicit rate is kept; a custom f needs equal
+    diagonal rates; rates outside (0, 2) are refused."""
+    assert L.bulk_rate(L.make_params(9, 4, 4, with_ns=True, nu=0.01)) == 1.0
+    assert L.bulk_rate(L.make_params(9, 4, 4, with_ns=True, nu=0.01, s_bulk_f=1.3)) == 1.3
+    assert L.bulk_rate(L.make_params(9, 4, 4, with_ns=True, nu=0.01, relax_f="srt")) == 0.0
+    assert L.bulk_rate(L.make_params(9, 4, 4, k=0.01)) == 0.0
+    s = np.full(27, 1.2)
+    assert L.bulk_rate(L.make_params(27, 4, 4, 4, with_ns=True, relax_f="custom", s_custom_f=s,
+                                     s_bulk_f=0.8)) == 0.8
+    s[8] = 1.3  # D3Q27 moment 020
+    for bad in (dict(relax_f="custom", s_custom_f=s, s_bulk_f=0.8), dict(nu=0.01, s_bulk_f=2.0),
+                dict(nu=0.01, s_bulk_f=-0.5)):
+        with pytest.raises(L.LBMError) as e:
+            L.relaxation_rates(L.make_params(27, 4, 4, 4, with_ns=True, **bad))
+        assert e.value.status == L.EINVAL
 
 
 def _random_geometry(rng, nx, ny, nz, Q):

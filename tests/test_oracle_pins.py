@@ -220,9 +220,71 @@ def test_ns_collision_conserves_momentum(oracle, Q):
         f = rng.uniform(0.01, 0.2, Q)
         rho = f.sum()
         u = (e.T @ f) / rho
-        out = oracle.collide_node(Q, f, u, oracle.preset(Q, "ns", oracle.s_main(0.02)))
-        assert out.sum() == pytest.approx(rho, abs=1e-15)
-        np.testing.assert_allclose(e.T @ out, e.T @ f, atol=1e-15)
+        for sb in (0.0, 1.0, 1.7):
+            out = oracle.collide_node(Q, f, u, oracle.preset(Q, "ns", oracle.s_main(0.02)), s_bulk=sb)
+            assert out.sum() == pytest.approx(rho, rel=2e-15)
+            np.testing.assert_allclose(e.T @ out, e.T @ f, atol=2e-15)
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+def test_trace_split_at_the_shear_rate_is_diagonal(oracle, Q):
+    """Relaxing the trace of the second-order block at the shear rate itself
+    is the diagonal relaxation; the equilibrium stays a fixed point for any
+    bulk rate."""
+    e, _, _ = oracle.lattice(Q)
+    rng = np.random.default_rng(11)
+    for cu in (False, True):
+        collide = oracle.collide_node_cu if cu else oracle.collide_node
+        for _ in range(4):
+            f = rng.uniform(0.01, 0.2, Q)
+            u = (e.T @ f) / f.sum()
+            sv = rng.uniform(1.2, 1.95)
+            s = oracle.preset(Q, "ns", sv)
+            np.testing.assert_allclose(collide(Q, f, u, s, s_bulk=sv), collide(Q, f, u, s), rtol=0, atol=2e-15)
+            geq = _product_eq(e, 1.1, u)
+            np.testing.assert_allclose(collide(Q, geq, u, s, s_bulk=1.0), geq, rtol=0, atol=1e-15)
+
+
+def _sound_damping(oracle, Q, nu, s_bulk, cu, Lx=64, t1=200, t2=1200):
+    """Standing sound wave rho = 1 + A cos(k x), u = 0, on an Lx x 1 (x 1)
+    periodic lattice: the acoustic energy sum(c_s^2 rho'^2 + u^2) decays as
+    exp(-2 G t) with G = nu_L k^2 / 2, nu_L = 2 nu (1 - 1/D) + zeta the
+    longitudinal viscosity of the linearised Navier-Stokes equations.  Returns
+    the measured G."""
+    N = Lx
+    kk = 2 * math.pi / Lx
+    rho = 1 + 1e-4 * np.cos(kk * np.arange(N))
+    sim = oracle.Sim(Q, Lx, 1, 1, with_ns=True, s_f=oracle.preset(Q, "ns", oracle.s_main(nu)),
+                     s_h=oracle.preset(Q, "trt", 1.0), cu_f=cu, s_bulk_f=s_bulk)
+    sim.init(np.ones(N), u=np.zeros((3, N)), rho=rho)
+
+    def energy():
+        r, uu, _ = sim.macroscopic()
+        return ((r - 1) ** 2 * CS2 + (uu ** 2).sum(axis=0)).sum()
+
+    sim.step(t1)
+    e1 = energy()
+    sim.step(t2 - t1)
+    return -math.log(energy() / e1) / (2 * (t2 - t1))
+
+
+@pytest.mark.parametrize("Q", [9, 27])
+@pytest.mark.parametrize("cu", [False, True], ids=["cm", "cumulant"])
+def test_sound_wave_damping_gives_bulk_viscosity(oracle, Q, cu):
+    """The trace of the second-order block relaxed at s_b gives the bulk
+    viscosity zeta = (2/D) c_s^2 (1/s_b - 1/2) (with s_b = s_nu: zeta =
+    (2/D) nu, the BGK value): the measured sound damping equals nu_L k^2 / 2
+    within 0.5 % for s_b = 1 and 1.5 and for the diagonal relaxation, on both
+    lattices and both collision families."""
+    nu = 0.01
+    D = 2 if Q == 9 else 3
+    kk = 2 * math.pi / 64
+    sv = oracle.s_main(nu)
+    for sb in (0.0, 1.0, 1.5):
+        zeta = (2.0 / D) * CS2 * (1.0 / (sb if sb > 0 else sv) - 0.5)
+        G = _sound_damping(oracle, Q, nu, sb, cu)
+        ref = (2 * nu * (1 - 1.0 / D) + zeta) * kk * kk / 2
+        assert G == pytest.approx(ref, rel=5e-3), (sb, G, ref)
 
 
 # ---------------------------------------------------------------------------
@@ -417,8 +479,9 @@ def test_nusselt_definition_on_outputs(oracle):
 
 
 def test_shear_wave_decay_gives_viscosity(oracle):
-    """f lattice, CM with second-order moments at s_nu = 1/(3 nu + 1/2): a shear
-    wave u_x = A sin(2 pi y / L) decays as exp(-nu k^2 t)."""
+    """f lattice, CM with the deviatoric second-order moments at s_nu =
+    1/(3 nu + 1/2) and their trace at 1: a shear wave u_x = A sin(2 pi y / L)
+    decays as exp(-nu k^2 t)."""
     for Q, dims in ((9, (2, 32, 1)), (27, (2, 32, 2))):
         nx, ny, nz = dims
         nu = 0.05
@@ -429,7 +492,7 @@ def test_shear_wave_decay_gives_viscosity(oracle):
         u = np.zeros((3, N))
         u[0] = A * np.sin(kk * y)
         sim = oracle.Sim(Q, nx, ny, nz, with_ns=True, s_f=oracle.preset(Q, "ns", oracle.s_main(nu)),
-                         s_h=oracle.preset(Q, "trt", 1.0))
+                         s_h=oracle.preset(Q, "trt", 1.0), s_bulk_f=1.0)
         sim.init(np.ones(N), u=u, rho=np.ones(N))
         T = 300
         sim.step(T)
