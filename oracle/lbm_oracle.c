@@ -673,29 +673,57 @@ int ora_collide(const ora_cfg *c, const double *f, const double *h, double *fs, 
 /* Cut links: every (non-solid x_b, direction i != 0) with x_b + e_i solid,
  * in increasing (node, direction) order.  q is the fraction of the link
  * vector between x_b and the wall (Sec. 3). */
+/* Cut links of node n (writes at most Q entries to out when non-NULL). */
+static int node_links(const ora_cfg *c, const ora_lat *L, long n, ora_link *out) {
+  long N = nnodes(c);
+  int cnt = 0;
+  if (ntype(c, n) == ORA_SOLID) return 0;
+  for (int a = 1; a < c->Q; a++) {
+    long w = neighbour(c, n, L->e[a], +1);
+    if (ntype(c, w) != ORA_SOLID) continue;
+    if (out) {
+      long xf = neighbour(c, n, L->e[a], -1);
+      out[cnt].node = (int32_t)n;
+      out[cnt].dir = a;
+      out[cnt].group = ngroup(c, w);
+      out[cnt].xf_solid = ntype(c, xf) == ORA_SOLID;
+      out[cnt].q = c->qlink ? c->qlink[(long)a * N + n] : 0.5;
+    }
+    cnt++;
+  }
+  return cnt;
+}
+
 long ora_links(const ora_cfg *c, ora_link *out, long cap) {
   ora_lat L;
-  long N, cnt = 0;
+  long N, total = 0;
+  long *first;
   if (check_cfg(c) || build_lattice(c->Q, &L)) return -1;
   if (!c->flags) return 0;
   N = nnodes(c);
+  /* count per node, then fill each node's run at its offset (node-major
+   * order, as a serial scan would produce it) */
+  first = (long *)malloc(sizeof(long) * (N + 1));
+  if (!first) return -1;
+#pragma omp parallel for schedule(static)
+  for (long n = 0; n < N; n++) first[n] = node_links(c, &L, n, NULL);
   for (long n = 0; n < N; n++) {
-    if (ntype(c, n) == ORA_SOLID) continue;
-    for (int a = 1; a < c->Q; a++) {
-      long w = neighbour(c, n, L.e[a], +1);
-      if (ntype(c, w) != ORA_SOLID) continue;
-      if (out && cnt < cap) {
-        long xf = neighbour(c, n, L.e[a], -1);
-        out[cnt].node = (int32_t)n;
-        out[cnt].dir = a;
-        out[cnt].group = ngroup(c, w);
-        out[cnt].xf_solid = ntype(c, xf) == ORA_SOLID;
-        out[cnt].q = c->qlink ? c->qlink[(long)a * N + n] : 0.5;
-      }
-      cnt++;
+    long k = first[n];
+    first[n] = total;
+    total += k;
+  }
+  first[N] = total;
+  if (out) {
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; n++) {
+      ora_link tmp[ORA_MAXQ];
+      int k = node_links(c, &L, n, tmp);
+      for (int j = 0; j < k; j++)
+        if (first[n] + j < cap) out[first[n] + j] = tmp[j];
     }
   }
-  return cnt;
+  free(first);
+  return total;
 }
 
 /* Interpolated bounce-back (Eq. IBB) for f; q = 1/2 without interpolation
@@ -731,7 +759,8 @@ int ora_stream(const ora_cfg *c, const double *fs, const double *hs, double *f, 
   if (check_cfg(c) || ctx_init(Q, &C)) return -1;
   N = nnodes(c);
 
-  /* 1. push streaming */
+  /* 1. push streaming (each target population has exactly one source) */
+#pragma omp parallel for schedule(static)
   for (long n = 0; n < N; n++) {
     if (ntype(c, n) == ORA_SOLID) continue;
     for (int a = 0; a < Q; a++) {
@@ -742,6 +771,7 @@ int ora_stream(const ora_cfg *c, const double *fs, const double *hs, double *f, 
     }
   }
   /* solid nodes keep their (unused) values */
+#pragma omp parallel for schedule(static)
   for (long n = 0; n < N; n++) {
     if (ntype(c, n) != ORA_SOLID) continue;
     for (int a = 0; a < Q; a++) {
@@ -758,6 +788,8 @@ int ora_stream(const ora_cfg *c, const double *fs, const double *hs, double *f, 
     if (!links) return -1;
     ora_links(c, links, nl);
   }
+  /* each link writes its own (node, opposite direction) population */
+#pragma omp parallel for schedule(static)
   for (li = 0; li < nl; li++) {
     const ora_link *k = &links[li];
     const ora_group *G = &c->groups[k->group];
@@ -785,37 +817,46 @@ int ora_stream(const ora_cfg *c, const double *fs, const double *hs, double *f, 
   }
   free(links);
 
-  /* 3. outlet (zero-gradient copy from x - 1 using values after step 2) */
+  /* 3. outlet (zero-gradient copy from x - 1 using values after step 2: the
+   * upstream values are read into a buffer before any outlet is written) */
   {
-    int has_outlet = 0;
-    for (long n = 0; n < N && !has_outlet; n++) has_outlet = ntype(c, n) == ORA_OUTLET;
-    if (has_outlet) {
-      f3 = c->with_ns ? (double *)malloc(sizeof(double) * Q * N) : NULL;
-      h3 = (double *)malloc(sizeof(double) * Q * N);
-      if (!h3 || (c->with_ns && !f3)) {
+    long no = 0, j = 0;
+    long *outl;
+    for (long n = 0; n < N; n++) no += ntype(c, n) == ORA_OUTLET;
+    if (no > 0) {
+      int ex[3] = {1, 0, 0};
+      outl = (long *)malloc(sizeof(long) * no);
+      f3 = (double *)malloc(sizeof(double) * Q * no);
+      h3 = (double *)malloc(sizeof(double) * Q * no);
+      if (!outl || !f3 || !h3) {
+        free(outl);
         free(f3);
         free(h3);
         return -1;
       }
-      if (c->with_ns) memcpy(f3, f, sizeof(double) * Q * N);
-      memcpy(h3, h, sizeof(double) * Q * N);
-      for (long n = 0; n < N; n++) {
-        int ex[3] = {1, 0, 0};
-        long up;
-        if (ntype(c, n) != ORA_OUTLET) continue;
-        up = neighbour(c, n, ex, -1);
+      for (long n = 0; n < N; n++)
+        if (ntype(c, n) == ORA_OUTLET) outl[j++] = n;
+      for (j = 0; j < no; j++) {
+        long up = neighbour(c, outl[j], ex, -1);
         for (int a = 0; a < Q; a++) {
-          if (C.L.e[a][0] >= 0) continue;
-          if (c->with_ns) f[a * N + n] = f3[a * N + up];
-          h[a * N + n] = h3[a * N + up];
+          if (c->with_ns) f3[j * Q + a] = f[a * N + up];
+          h3[j * Q + a] = h[a * N + up];
         }
       }
+      for (j = 0; j < no; j++)
+        for (int a = 0; a < Q; a++) {
+          if (C.L.e[a][0] >= 0) continue;
+          if (c->with_ns) f[a * N + outl[j]] = f3[j * Q + a];
+          h[a * N + outl[j]] = h3[j * Q + a];
+        }
+      free(outl);
       free(f3);
       free(h3);
     }
   }
 
   /* 4. EQ nodes */
+#pragma omp parallel for schedule(static)
   for (long n = 0; n < N; n++) {
     double u[3], geq[ORA_MAXQ];
     const ora_group *G;

@@ -1,0 +1,168 @@
+"""Writes the FP64 oracle goldens of the long parity runs (test infrastructure).
+
+Each golden is the oracle's canonical state after the stated step count of one
+workload, on the seeded inputs of ``paper_2203_01316_amd/workloads.py``, with
+the relaxation rates of Sec. 2.1.1 taken from the oracle's own presets.  Only
+the oracle computes anything here; the GPU tests compare the library against
+these files.  Velocity fields that the FP32 library stores are rounded to FP32
+first, so that both sides advect with the same field.
+
+    python tests/golden/make_goldens.py            # every golden
+    python tests/golden/make_goldens.py c2 c4_64   # some of them
+
+Goldens (compressed .npz, no pickles):
+  c2_channel_1024x256_t20000  advection-diffusion channel, 20,000 steps:
+      H on every node (FP32), h at every boundary-record node (FP64)
+  c3_cylinder_2048_t200       coupled heated cylinder 2048^2, 200 steps:
+      f and h at the cylinder's boundary nodes and their neighbours, the
+      inlet and outlet columns and 2048 random nodes (FP32); mass, energy,
+      heater flux and two section fluxes (FP64)
+  c4_tgv_64_t200, c4_tgv_256_t10   D3Q27 Taylor-Green vortex, central
+      moments (and c4_tgv_64_cu_t200 with the cumulant pair): f and h at
+      2048 random nodes (FP32), mass and energy (FP64)
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from oracle import oracle as O  # noqa: E402
+from paper_2203_01316_amd import workloads as W  # noqa: E402
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _step_logged(sim, steps, name, every=1000):
+    t0 = time.time()
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        sim.step(k)
+        done += k
+        _log(f"{name}: {done}/{steps} steps, {time.time() - t0:.0f} s")
+
+
+def _boundary_nodes(sim, flags):
+    links = sim.links()
+    t = flags & 15
+    nodes = set(int(n) for n in links["node"])
+    nodes |= set(int(n) for n in np.nonzero((t == W.EQ) | (t == W.OUTLET))[0])
+    return np.array(sorted(nodes), dtype=np.int64)
+
+
+def c2():
+    """Config 2: 1024x256 channel, Poiseuille u_max = 0.05, ABB walls H = 0,
+    EQ inlet H = 1, outlet, IABB disc r = 20 at (256, 128) H = 2, k = 0.005,
+    CM-TRT, 20,000 steps."""
+    nx, ny, T = 1024, 256, 20000
+    flags, q, groups, u = W.channel(nx, ny, 256, 128, 20, 0.05)
+    sim = O.Sim(9, nx, ny, s_h=O.preset(9, "trt", O.s_main(0.005)), uvel=f32(u), flags=flags, qlink=q,
+                groups=groups)
+    sim.init(np.zeros(nx * ny))
+    _step_logged(sim, T, "c2")
+    _, h = sim.pre()
+    _, _, H = sim.macroscopic()
+    bn = _boundary_nodes(sim, flags)
+    return "c2_channel_1024x256_t20000", dict(t=T, H=H.astype(np.float32), nodes=bn, h_nodes=h[:, bn],
+                                              sum_H=H.sum())
+
+
+def _sample(n, k, seed):
+    return np.sort(np.random.Generator(np.random.PCG64(seed)).choice(n, k, replace=False)).astype(np.int64)
+
+
+def c3():
+    """Config 3 parity window: coupled 2048^2 heated cylinder r = 64, Re = 100
+    (nu = 0.04 * 128 / 100), Pr = 0.71, CM-NS f (trace at 1) and CM-TRT h,
+    200 steps."""
+    nx = ny = 2048
+    T = 200
+    nu = 0.04 * 128 / 100.0
+    k = nu / 0.71
+    flags, q, groups, u, rho0, H0 = W.heated_cylinder(nx, ny, 64, u_in=0.04, amp=1e-3, seed=0)
+    uu = f32(u)
+    sim = O.Sim(9, nx, ny, with_ns=True, s_f=O.preset(9, "ns", O.s_main(nu)), s_h=O.preset(9, "trt", O.s_main(k)),
+                uvel=uu, flags=flags, qlink=q, groups=groups, s_bulk_f=1.0)
+    sim.init(H0, u=uu, rho=rho0)
+    _step_logged(sim, T, "c3", every=20)
+    f, h, flux = sim.pre(with_flux=True)
+    rho, _, H = sim.macroscopic()
+    links = sim.links()
+    n = nx * ny
+    cyl = np.unique(links["node"][links["group"] == 1]).astype(np.int64)
+    x, y = cyl % nx, cyl // nx
+    near = set()
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            near |= set(((x + dx) % nx + nx * ((y + dy) % ny)).tolist())
+    cols = np.concatenate([np.arange(ny) * nx, np.arange(ny) * nx + nx - 1])
+    nodes = np.array(sorted(near | set(cols.tolist()) | set(_sample(n, 2048, 30).tolist())), dtype=np.int64)
+    nodes = nodes[(flags[nodes] & 15) != W.SOLID]
+    sections = (50, nx - 101)
+    return "c3_cylinder_2048_t200", dict(
+        t=T, nodes=nodes, f_nodes=f[:, nodes].astype(np.float32), h_nodes=h[:, nodes].astype(np.float32),
+        boundary=cyl, sum_rho=rho.sum(), sum_H=H.sum(), q_surface=flux[links["group"] == 1].sum(),
+        sections=np.array(sections), q_sections=np.array([sim.section_flux(X, h) for X in sections]))
+
+
+def _tgv(n1, T, cu, name):
+    rho, u, H = W.taylor_green_3d(n1, 0.04)
+    nu = 0.002
+    sim = O.Sim(27, n1, n1, n1, with_ns=True, s_f=O.preset(27, "ns", O.s_main(nu)),
+                s_h=O.preset(27, "1st" if cu else "trt", O.s_main(0.002)), cu_f=cu, cu_h=cu, s_bulk_f=1.0)
+    sim.init(H, u=u, rho=rho)
+    del rho, u, H
+    _step_logged(sim, T, name, every=10 if n1 > 64 else 25)
+    f, h = sim.pre()
+    nodes = _sample(n1 ** 3, 2048, 40 + n1)
+    out = dict(t=T, nodes=nodes, f_nodes=f[:, nodes].astype(np.float32), h_nodes=h[:, nodes].astype(np.float32),
+               sum_rho=f.sum(), sum_H=h.sum())
+    return name, out
+
+
+def c4_64():
+    """Config 4 at 64^3: Taylor-Green vortex u0 = 0.04, nu = k = 0.002,
+    CM-NS f and CM-TRT h, 200 steps."""
+    return _tgv(64, 200, False, "c4_tgv_64_t200")
+
+
+def c4_64_cu():
+    """The same with the cumulant f and Cumulants-1st h."""
+    return _tgv(64, 200, True, "c4_tgv_64_cu_t200")
+
+
+def c4_256():
+    """Config 4 at its full 256^3, 10 steps (central moments)."""
+    return _tgv(256, 10, False, "c4_tgv_256_t10")
+
+
+GOLDENS = {"c2": c2, "c3": c3, "c4_64": c4_64, "c4_64_cu": c4_64_cu, "c4_256": c4_256}
+
+
+def main(names):
+    O.build()
+    for key in names or list(GOLDENS):
+        t0 = time.time()
+        name, data = GOLDENS[key]()
+        path = os.path.join(HERE, name + ".npz")
+        np.savez_compressed(path, **data)
+        _log(f"wrote {path} ({os.path.getsize(path) / 1e6:.2f} MB, {time.time() - t0:.0f} s, "
+             f"{O.lib().ora_threads()} threads)")
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
