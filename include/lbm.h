@@ -275,6 +275,21 @@ lbm_status lbm_set_populations(lbm_ctx *ctx, int32_t lattice, const double *src_
 lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32_t n_columns,
                       double *out, int32_t nout);
 
+/* lbm_reduce() for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same outputs, computed by the same kernels, with the scratch of the
+ * reduction (first-pass partial sums, the device result vector and the
+ * column list, 17,176 bytes) in a static device array that each GPU holds
+ * once for the life of the process, instead of the context's workspace.  The
+ * macroscopic pass still writes its per-node fields into the workspace the
+ * caller gave lbm_create().  Allocates nothing (no hipMalloc, hipFree or
+ * allocating library call).  n_columns above 64, the array's capacity, is
+ * LBM_EINVAL.  Calls on one GPU share that array: calls that overlap on one
+ * GPU (from several threads or streams) race; every call overwrites what it
+ * reads.  Synchronises. */
+lbm_status lbm_reduce_noalloc(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32_t n_columns, double *out,
+                              int32_t nout);
+
 /* Nusselt number of a heated body (Sec. 4.4: Nu = varsigma D / k with
  * varsigma = qdot / (pi D (T_wall - T_in)); heat fluxes of Eqs.
  * heat_flux_thorough_heater and heat_flux_section), in FP64 from the

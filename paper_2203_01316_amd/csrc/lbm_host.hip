@@ -16,6 +16,21 @@
 
 using namespace lbm;
 
+// Static device scratch of lbm_reduce_noalloc(): the partial sums of the
+// first reduction pass, the result vector and the column list.  One copy per
+// GPU, held until the process ends.  In host code `scratch` is only a
+// stand-in: its device address comes from hipGetSymbolAddress (per device).
+namespace {
+constexpr int kScratchPartials = 1024;
+constexpr int kScratchColumns = 64;
+constexpr size_t kScratchBytes =
+    sizeof(double) * (2 * kScratchPartials + 3 + kScratchColumns) + sizeof(int32_t) * kScratchColumns;
+constexpr int kMaxDevices = 64;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static void *g_scratch_ptr[kMaxDevices];
+static bool g_scratch_set[kMaxDevices];
+
 static_assert(sizeof(DevLink) == sizeof(lbm_link), "link layout");
 static_assert(sizeof(DevGroup) == sizeof(lbm_group), "group layout");
 
@@ -693,6 +708,24 @@ lbm_status lbm_create(const lbm_params *p, void *workspace_dev, void *hip_stream
     g_err = "hipGetDevice failed";
     return LBM_EDEVICE;
   }
+  // device address of the static scratch, looked up once per device with
+  // that device current (each GPU holds its own copy of the array)
+  if (ctx->device < 0 || ctx->device >= kMaxDevices) {
+    delete ctx;
+    set_err(nullptr, "device index outside [0, %d)", kMaxDevices);
+    return LBM_EDEVICE;
+  }
+  if (!g_scratch_set[ctx->device]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      delete ctx;
+      set_err(nullptr, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+      return LBM_EDEVICE;
+    }
+    g_scratch_ptr[ctx->device] = ptr;
+    g_scratch_set[ctx->device] = true;
+  }
   ctx->ws = static_cast<char *>(workspace_dev);
   ctx->L = layout(p);
   ctx->cur = 0;
@@ -930,8 +963,10 @@ lbm_status lbm_set_populations(lbm_ctx *ctx, int32_t lattice, const double *src_
   return rebuild_side(ctx);
 }
 
-lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32_t n_columns, double *out,
-                      int32_t nout) {
+// Reductions of lbm_reduce with their scratch (partials of the first pass,
+// the device result vector, the device column list) at the given addresses.
+static lbm_status reduce_impl(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32_t n_columns, double *out,
+                              int32_t nout, double *part, int npart, double *res, int32_t *cols) {
   CTX_CHECK(ctx);
   if (n_columns < 0 || n_columns > kMaxColumns || (n_columns > 0 && !columns)) {
     set_err(&ctx->err, "n_columns must be in [0, %d]", kMaxColumns);
@@ -952,8 +987,6 @@ lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32
   double *H = reinterpret_cast<double *>(ctx->ws + ctx->L.off_H);
   double *qx = reinterpret_cast<double *>(ctx->ws + ctx->L.off_qx);
   double *flux = reinterpret_cast<double *>(ctx->ws + ctx->L.off_flux);
-  double *res = reinterpret_cast<double *>(ctx->ws + ctx->L.off_res);
-  int32_t *cols = reinterpret_cast<int32_t *>(ctx->ws + ctx->L.off_cols);
   KArgs a = make_args(ctx, ctx->cur);
   a.out0 = ctx->p.with_ns ? rho : nullptr;
   a.out2 = H;
@@ -966,8 +999,8 @@ lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32
                                 ctx->stream), "copy columns");
   HIP_TRY(ctx, launch_reduce(ctx->p.with_ns ? rho : nullptr, H, qx, ctx->n, ctx->p.nx, ctx->p.ny, ctx->p.nz, cols,
                              n_columns, flux, reinterpret_cast<const DevLink *>(ctx->ws + ctx->L.off_links),
-                             ctx->geom ? ctx->nlinks : 0, group, reinterpret_cast<double *>(ctx->ws + ctx->L.off_part),
-                             kPartials, res, ctx->stream), "reduction launch");
+                             ctx->geom ? ctx->nlinks : 0, group, part, npart, res, ctx->stream),
+          "reduction launch");
   double host[3 + kMaxColumns];
   HIP_TRY(ctx, hipMemcpyAsync(host, res, sizeof(double) * (3 + n_columns), hipMemcpyDeviceToHost, ctx->stream),
           "copy reductions");
@@ -979,6 +1012,35 @@ lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32
     return LBM_EDIVERGED;
   }
   return LBM_OK;
+}
+
+lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32_t n_columns, double *out,
+                      int32_t nout) {
+  CTX_CHECK(ctx);
+  return reduce_impl(ctx, group, columns, n_columns, out, nout,
+                     reinterpret_cast<double *>(ctx->ws + ctx->L.off_part), kPartials,
+                     reinterpret_cast<double *>(ctx->ws + ctx->L.off_res),
+                     reinterpret_cast<int32_t *>(ctx->ws + ctx->L.off_cols));
+}
+
+lbm_status lbm_reduce_noalloc(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32_t n_columns, double *out,
+                              int32_t nout) {
+  CTX_CHECK(ctx);
+  static_assert(kScratchPartials == kPartials && kScratchColumns == kMaxColumns, "scratch sizes");
+  if (n_columns > kScratchColumns) {
+    set_err(&ctx->err, "n_columns = %d exceeds the static scratch (at most %d columns)", n_columns,
+            kScratchColumns);
+    return LBM_EINVAL;
+  }
+  if (!g_scratch_set[ctx->device]) {
+    set_err(&ctx->err, "static scratch not set up on device %d", ctx->device);
+    return LBM_ESTATE;
+  }
+  char *base = static_cast<char *>(g_scratch_ptr[ctx->device]);
+  double *part = reinterpret_cast<double *>(base);
+  double *res = part + 2 * kScratchPartials;
+  int32_t *cols = reinterpret_cast<int32_t *>(res + 3 + kScratchColumns);
+  return reduce_impl(ctx, group, columns, n_columns, out, nout, part, kScratchPartials, res, cols);
 }
 
 lbm_status lbm_nusselt(lbm_ctx *ctx, int32_t group, int32_t x_in, int32_t x_out, double T_wall, double T_in,

@@ -80,6 +80,7 @@ _sig = {
     "lbm_set_populations": (C.c_int, [_vp, C.c_int32, _vp, C.c_int64]),
     "lbm_reduce": (C.c_int, [_vp, C.c_int32, _vp, C.c_int32, _vp, C.c_int32]),
     "lbm_nusselt": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double, _vp, C.c_int32]),
+    "lbm_reduce_noalloc": (C.c_int, [_vp, C.c_int32, _vp, C.c_int32, _vp, C.c_int32]),
     "lbm_state_bytes": (C.c_size_t, [_vp]),
     "lbm_save_state": (C.c_int, [_vp, _vp]),
     "lbm_load_state": (C.c_int, [_vp, _vp]),
@@ -342,6 +343,15 @@ class LBM:
         out = np.zeros(3 + len(cols))
         self._ck(_lib.lbm_reduce(self.ctx, int(group), cols.ctypes.data if len(cols) else None, len(cols),
                                  out.ctypes.data, len(out)))
+        return out
+
+    def reduce_noalloc(self, group=0, columns=()):
+        """lbm_reduce_noalloc: reduce() with its scratch in the library's static
+        device array (no allocation by the library)."""
+        cols = np.ascontiguousarray(np.asarray(columns, dtype=np.int32).reshape(-1))
+        out = np.zeros(3 + len(cols))
+        self._ck(_lib.lbm_reduce_noalloc(self.ctx, int(group), cols.ctypes.data if len(cols) else None, len(cols),
+                                         out.ctypes.data, len(out)))
         return out
 
     def nusselt(self, group, x_in, x_out, T_wall, T_in):
