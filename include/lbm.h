@@ -206,6 +206,15 @@ lbm_status lbm_count_geometry(const lbm_params *p, const uint16_t *flags, int64_
 lbm_status lbm_build_links(const lbm_params *p, const uint16_t *flags, const double *q,
                            int32_t n_groups, lbm_link *out, int64_t cap, int64_t *count);
 
+/* Measurement aid, not part of the method: a streaming device-to-device copy
+ * of `bytes` (a multiple of 16; both pointers 16-byte aligned, regions not
+ * overlapping) with 16-byte non-temporal loads and stores, on
+ * hip_stream (NULL = default), asynchronous.  blocks = 0 launches one 16-byte
+ * vector per thread, blocks > 0 a grid-stride loop over that many 256-thread
+ * blocks.  Its rate is the practical HBM ceiling against which the step
+ * kernels are read (2 x bytes moved per call). */
+lbm_status lbm_device_copy(void *dst_dev, const void *src_dev, size_t bytes, int32_t blocks, void *hip_stream);
+
 /* Last error message of ctx (or of the calling thread when ctx is NULL). */
 const char *lbm_last_error(const lbm_ctx *ctx);
 

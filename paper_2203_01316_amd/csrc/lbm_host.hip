@@ -1023,6 +1023,22 @@ lbm_status lbm_reduce(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32
                      reinterpret_cast<int32_t *>(ctx->ws + ctx->L.off_cols));
 }
 
+lbm_status lbm_device_copy(void *dst_dev, const void *src_dev, size_t bytes, int32_t blocks, void *hip_stream) {
+  if (!dst_dev || !src_dev || bytes % 16 != 0 || reinterpret_cast<uintptr_t>(dst_dev) % 16 != 0 ||
+      reinterpret_cast<uintptr_t>(src_dev) % 16 != 0 || blocks < 0) {
+    set_err(nullptr, "lbm_device_copy: needs non-NULL 16-byte aligned pointers, a multiple of 16 bytes and "
+            "blocks >= 0");
+    return LBM_EINVAL;
+  }
+  const hipError_t e = launch_copy16(src_dev, dst_dev, (int64_t)(bytes / 16), blocks,
+                                     static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) {
+    set_err(nullptr, "lbm_device_copy launch: %s", hipGetErrorString(e));
+    return LBM_EDEVICE;
+  }
+  return LBM_OK;
+}
+
 lbm_status lbm_reduce_noalloc(lbm_ctx *ctx, int32_t group, const int32_t *columns, int32_t n_columns, double *out,
                               int32_t nout) {
   CTX_CHECK(ctx);

@@ -145,6 +145,28 @@ __global__ void __launch_bounds__(256) k_column_sum(const double *qx, int nx, in
   if (threadIdx.x == 0) out[3 + blockIdx.x] = s;
 }
 
+// Streaming copy that measures the practical HBM ceiling: 16-byte
+// non-temporal loads and stores (measured fastest of plain / non-temporal
+// loads and stores and 1-8 vectors per thread); blocks = 0: one vector per
+// thread, else a grid-stride loop over that many blocks.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_copy16(const v4f *__restrict__ src, v4f *__restrict__ dst, int64_t n16) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) {
+    const v4f v = __builtin_nontemporal_load(&src[i]);
+    __builtin_nontemporal_store(v, &dst[i]);
+  }
+}
+
+hipError_t launch_copy16(const void *src, void *dst, int64_t n16, int blocks, hipStream_t s) {
+  if (n16 <= 0) return hipSuccess;
+  const int64_t one_each = (n16 + 255) / 256;
+  const int64_t g = blocks > 0 && blocks < one_each ? blocks : one_each;
+  k_copy16<<<(unsigned)g, 256, 0, s>>>(static_cast<const v4f *>(src), static_cast<v4f *>(dst), n16);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce(const double *rho, const double *H, const double *qx, int64_t n, int nx, int ny, int nz,
                          const int32_t *cols, int ncols, const double *link_flux, const DevLink *links, int64_t nlinks,
                          int group, double *partials, int npartials, double *out, hipStream_t s) {

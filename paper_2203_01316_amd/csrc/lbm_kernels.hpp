@@ -156,6 +156,7 @@ hipError_t launch_reduce(const double *rho, const double *H, const double *qx, i
                          int ny, int nz, const int32_t *cols, int ncols, const double *link_flux,
                          const DevLink *links, int64_t nlinks, int group, double *partials,
                          int npartials, double *out, hipStream_t s);
+hipError_t launch_copy16(const void *src, void *dst, int64_t n16, int blocks, hipStream_t s);
 hipError_t launch_adjoint(int Q, bool fp64, const KArgs &a, const void *lam_next, void *lam_prev, void *dJdQ,
                           hipStream_t s);
 // cls: node classes or null; solid nodes are left out of the objective.

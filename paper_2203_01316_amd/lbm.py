@@ -11,6 +11,9 @@ import ctypes as C
 import os
 
 import numpy as np
+# torch first: it loads the HIP runtime that the library then shares (loading
+# the library first brings in a second runtime copy, whose device calls fail)
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
@@ -81,6 +84,7 @@ _sig = {
     "lbm_reduce": (C.c_int, [_vp, C.c_int32, _vp, C.c_int32, _vp, C.c_int32]),
     "lbm_nusselt": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double, _vp, C.c_int32]),
     "lbm_reduce_noalloc": (C.c_int, [_vp, C.c_int32, _vp, C.c_int32, _vp, C.c_int32]),
+    "lbm_device_copy": (C.c_int, [_vp, _vp, C.c_size_t, C.c_int32, _vp]),
     "lbm_state_bytes": (C.c_size_t, [_vp]),
     "lbm_save_state": (C.c_int, [_vp, _vp]),
     "lbm_load_state": (C.c_int, [_vp, _vp]),
@@ -165,6 +169,15 @@ def bulk_rate(p: Params) -> float:
     sb = C.c_double()
     _check(_lib.lbm_relaxation_rates(C.byref(p), None, None, C.byref(sb)))
     return float(sb.value)
+
+
+def device_copy(dst, src, blocks=0, hip_stream=None):
+    """lbm_device_copy of the torch tensor src into dst (same byte size)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("dst and src sizes differ")
+    _check(_lib.lbm_device_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes, int(blocks),
+                                hip_stream))
 
 
 def _host_flags(flags):
