@@ -12,7 +12,7 @@ first, so that both sides advect with the same field.
 
 Goldens (compressed .npz, no pickles):
   c2_channel_1024x256_t20000  advection-diffusion channel, 20,000 steps:
-      H on every node (FP32), h at every boundary-record node (FP64)
+      H on every node and h at every boundary-record node (FP64)
   c3_cylinder_2048_t200       coupled heated cylinder 2048^2, 200 steps:
       f and h at the cylinder's boundary nodes and their neighbours, the
       inlet and outlet columns and 2048 random nodes (FP32); mass, energy,
@@ -77,8 +77,7 @@ def c2():
     _, h = sim.pre()
     _, _, H = sim.macroscopic()
     bn = _boundary_nodes(sim, flags)
-    return "c2_channel_1024x256_t20000", dict(t=T, H=H.astype(np.float32), nodes=bn, h_nodes=h[:, bn],
-                                              sum_H=H.sum())
+    return "c2_channel_1024x256_t20000", dict(t=T, H=H, nodes=bn, h_nodes=h[:, bn], sum_H=H.sum())
 
 
 def _sample(n, k, seed):
