@@ -288,11 +288,26 @@ __device__ __forceinline__ void bulk_shift(R *K, R t_pre, R teq, R db) {
   if constexpr (D == 3) K[diag2<D>(2)] += d;
 }
 
+// Moments whose rate the caller guarantees to be exactly 1 (compile time),
+// by total order m + n + o: RATE1_NONE none; RATE1_ORD3 every order >= 3 (the
+// hydrodynamic preset); RATE1_EVEN every even order, 0 included (CM-TRT);
+// RATE1_ORD2 order 0 and every order >= 2 (CM-1st).  Such a moment takes its
+// equilibrium directly, so its pre-collision value is never used and the
+// forward transform drops the arithmetic that only feeds it.
+enum : int { RATE1_NONE = 0, RATE1_ORD3 = 1, RATE1_EVEN = 2, RATE1_ORD2 = 3 };
+__host__ __device__ constexpr bool rate_is_one(int pattern, int order) {
+  return pattern == RATE1_ORD3 ? order >= 3
+         : pattern == RATE1_EVEN ? order % 2 == 0
+         : pattern == RATE1_ORD2 ? order != 1
+                                 : false;
+}
+
 // Relaxation toward the central-moment equilibrium, in place on the central
 // moments K (chimera order), rates s (chimera order).  psi is the conserved
 // zeroth moment used by the equilibrium; src the source of App. D (0 if none).
-// TR: the trace of the second-order block relaxes at s_200 + db.
-template <int D, class R, bool TR = false>
+// TR: the trace of the second-order block relaxes at s_200 + db.  ONE: a
+// RATE1_* pattern of rates known to be 1.
+template <int D, class R, bool TR = false, int ONE = RATE1_NONE>
 __device__ __forceinline__ void relax(R *K, const R *s, R psi, R src, R db = R(0)) {
   constexpr int NQ = D == 2 ? 9 : 27;
   R t_pre = R(0);
@@ -303,7 +318,9 @@ __device__ __forceinline__ void relax(R *K, const R *s, R psi, R src, R db = R(0
     const int n = D == 2 ? k % 3 : (k / 3) % 3;
     const int o = D == 2 ? 0 : k % 3;
     const R c = ceq1<R>(m) * ceq1<R>(n) * ceq1<R>(o);
-    if (c == R(0))
+    if (rate_is_one(ONE, m + n + o))
+      K[k] = psi * c;
+    else if (c == R(0))
       K[k] = K[k] - s[k] * K[k];
     else
       K[k] = K[k] + s[k] * (psi * c - K[k]);
@@ -314,11 +331,11 @@ __device__ __forceinline__ void relax(R *K, const R *s, R psi, R src, R db = R(0
 
 // Full central-moment collision of one lattice (chimera slots in, chimera
 // slots out): g* = T(u)^-1 [Y~ + S (Y~eq - Y~)].
-template <int D, class R, bool TR = false>
+template <int D, class R, bool TR = false, int ONE = RATE1_NONE>
 __device__ __forceinline__ void collide(R *g, const R *s, R ux, R uy, R uz, R src, R db = R(0)) {
   to_central<D, R>(g, ux, uy, uz);
   const R psi = g[0] + R(0.5) * src;
-  relax<D, R, TR>(g, s, psi, src, db);
+  relax<D, R, TR, ONE>(g, s, psi, src, db);
   from_central<D, R>(g, ux, uy, uz);
 }
 

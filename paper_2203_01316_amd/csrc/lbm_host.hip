@@ -525,6 +525,19 @@ static int top_rate_order(int Q, const double *sc) {
   return top;
 }
 
+// Whether every rate (chimera order) of a class of moments is exactly 1:
+// cls 3 every order >= 3; cls 1 every even order (0 included); cls 2 order 0
+// and every order >= 2.
+static bool rates_one_where(int Q, const double *sc, int cls) {
+  for (int k = 0; k < Q; k++) {
+    const int m = Q == 9 ? k / 3 : k / 9, n = Q == 9 ? k % 3 : (k / 3) % 3, o = Q == 9 ? 0 : k % 3;
+    const int order = m + n + o;
+    const bool in = cls == 3 ? order >= 3 : cls == 1 ? order % 2 == 0 : order != 1;
+    if (in && sc[k] != 1.0) return false;
+  }
+  return true;
+}
+
 static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   KArgs a;
   memset(&a, 0, sizeof(a));
@@ -749,6 +762,22 @@ lbm_status lbm_create(const lbm_params *p, void *workspace_dev, void *hip_stream
   if (p->cumulant && (!(p->cumulant & 2) || top_rate_order(ctx->Q, ctx->sfc) <= 2) &&
       (!(p->cumulant & 1) || top_rate_order(ctx->Q, ctx->shc) <= 1))
     ctx->cu_kernel |= 4;
+  // central-moment lattices whose rates are 1 on a whole class of orders take
+  // those moments' equilibria directly (the hydrodynamic preset for f,
+  // CM-TRT or CM-1st for h): bits 3, 4 and 5 of the collision selector, for
+  // the combinations the kernels are built for
+  {
+    int pat = 0;
+    if (p->with_ns && !(p->cumulant & 2) && rates_one_where(ctx->Q, ctx->sfc, 3)) pat |= 8;
+    if (!(p->cumulant & 1)) {
+      if (rates_one_where(ctx->Q, ctx->shc, 2))
+        pat |= 32;
+      else if (rates_one_where(ctx->Q, ctx->shc, 1))
+        pat |= 16;
+    }
+    const int sel = ctx->cu_kernel | pat;
+    if (sel == 8 || sel == 16 || sel == 22 || sel == 24 || sel == 32 || sel == 40) ctx->cu_kernel = sel;
+  }
   *out = ctx;
   return LBM_OK;
 }

@@ -30,6 +30,8 @@
 // updates its upstream node, reading both before writing either.
 #pragma once
 
+#include <type_traits>
+
 #include "lbm_device.hpp"
 #include "lbm_kernels.hpp"
 
@@ -139,6 +141,23 @@ __device__ __forceinline__ global_ptr<E> uniform_base(E *p) {
 // slots per tile (FP64/FP32) or the plane stride (FP16) of the layout.  The
 // deviation storages keep g_i - w_i g_ref; w_i = w_opp(i), so a swapped slot
 // needs no other weight.
+// 2-byte planes: the element's byte offset 2m (m < 2^31) fits in 32 bits, so
+// the access is a scalar plane base plus one zero-extended 32-bit lane offset,
+// which the pulls of both lattices from one node share (the scalar-base form
+// of the global loads and stores); wider elements use 64-bit offsets.
+template <class S, class P>
+__device__ __forceinline__ P elem_at(P p, uint64_t off) {
+  if constexpr (sizeof(S) == 2) {
+    using C = typename std::conditional<std::is_const<typename std::remove_pointer<P>::type>::value,
+                                        __attribute__((address_space(1))) const char,
+                                        __attribute__((address_space(1))) char>::type;
+    const uint32_t b = (uint32_t)off * 2u;
+    return (P)((C *)p + (uint64_t)b);
+  } else {
+    return p + off;
+  }
+}
+
 template <int Q, int ST, int NL = 0>
 __device__ __forceinline__ typename StT<ST>::R ldp(const void *base, int slot, int64_t ps, int64_t m,
                                                    typename StT<ST>::R ref) {
@@ -146,7 +165,7 @@ __device__ __forceinline__ typename StT<ST>::R ldp(const void *base, int slot, i
   using R = typename T::R;
   const global_ptr<const typename T::S> p =
       uniform_base(static_cast<const typename T::S *>(base) + slot_offset<Q, typename T::S>(slot, ps));
-  R v = StoreT<typename T::S>::ld(p + node_offset<Q, typename T::S, NL>(ps, m));
+  R v = StoreT<typename T::S>::ld(elem_at<typename T::S>(p, node_offset<Q, typename T::S, NL>(ps, m)));
   if constexpr (T::DEV) v += weight<Q, R>(slot) * ref;
   return v;
 }
@@ -158,7 +177,7 @@ __device__ __forceinline__ void stp(void *base, int slot, int64_t ps, int64_t m,
   if constexpr (T::DEV) v -= weight<Q, typename T::R>(slot) * ref;
   const global_ptr<typename T::S> p =
       uniform_base(static_cast<typename T::S *>(base) + slot_offset<Q, typename T::S>(slot, ps));
-  StoreT<typename T::S>::st(p + node_offset<Q, typename T::S, NL>(ps, m), v);
+  StoreT<typename T::S>::st(elem_at<typename T::S>(p, node_offset<Q, typename T::S, NL>(ps, m)), v);
 }
 
 // Value a store followed by a load of population i would return.
@@ -355,7 +374,7 @@ __device__ __forceinline__ void post_addr(const KArgs &a, Node c, int64_t m, int
 // measured faster for them.
 template <int Q, int LAY, int CU>
 __device__ __forceinline__ constexpr bool split_order() {
-  return (Lat<Q>::D == 3 || LAY != LAY_AB) && (CU == 0 || (CU & 4));
+  return (Lat<Q>::D == 3 || LAY != LAY_AB) && ((CU & 7) == 0 || (CU & 4));
 }
 
 // ---------------------------------------------------------------------------
@@ -388,7 +407,8 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
       else if constexpr (CU & 2)
         collide_cu<D, R, 0, true>(g, rates<R>(a, true), ux, uy, uz, R(0), bulk_delta<R>(a));
       else
-        collide<D, R, true>(g, rates<R>(a, true), ux, uy, uz, R(0), bulk_delta<R>(a));
+        collide<D, R, true, (CU & 8) ? RATE1_ORD3 : RATE1_NONE>(g, rates<R>(a, true), ux, uy, uz, R(0),
+                                                                 bulk_delta<R>(a));
 #pragma unroll
       for (int k = 0; k < Q; k++) {
         const int i = split_order<Q, LAY, CU>() ? dir_at_pos<Q>(k) : k;
@@ -406,7 +426,8 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
     else if constexpr (CU & 1)
       collide_cu<D, R>(g, rates<R>(a, false), ux, uy, uz, src);
     else
-      collide<D, R>(g, rates<R>(a, false), ux, uy, uz, src);
+      collide<D, R, false, (CU & 32) ? RATE1_ORD2 : (CU & 16) ? RATE1_EVEN : RATE1_NONE>(g, rates<R>(a, false), ux,
+                                                                                          uy, uz, src);
 #pragma unroll
     for (int k = 0; k < Q; k++) {
       const int i = split_order<Q, LAY, CU>() ? dir_at_pos<Q>(k) : k;
@@ -1078,11 +1099,14 @@ static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b -
   }
 
 // cu (bit 0 h, bit 1 f: cumulant collision; bit 2: order-limited cumulant
-// transform) as a compile-time CU for CALL; f bits need the hydrodynamic
-// lattice, bit 2 a cumulant bit.
+// transform; bit 3: central-moment f with every rate of order >= 3 equal to
+// 1; bits 4 / 5: central-moment h with every even-order rate / every rate but
+// the first order equal to 1) as a compile-time CU for CALL; f bits need the
+// hydrodynamic lattice, bit 2 a cumulant bit.  The host picks the rate bits
+// only for the combinations listed here.
 #define LBM_CU_CASE(NS_VAL, V, CALL)       \
   case V:                                   \
-    if constexpr (!((V) & 2) || NS_VAL) {   \
+    if constexpr (!((V) & 10) || NS_VAL) {  \
       constexpr int CU = V;                 \
       CALL;                                 \
       break;                                \
@@ -1098,6 +1122,12 @@ static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b -
     LBM_CU_CASE(NS_VAL, 5, CALL)              \
     LBM_CU_CASE(NS_VAL, 6, CALL)              \
     LBM_CU_CASE(NS_VAL, 7, CALL)              \
+    LBM_CU_CASE(NS_VAL, 8, CALL)              \
+    LBM_CU_CASE(NS_VAL, 16, CALL)             \
+    LBM_CU_CASE(NS_VAL, 22, CALL)             \
+    LBM_CU_CASE(NS_VAL, 24, CALL)             \
+    LBM_CU_CASE(NS_VAL, 32, CALL)             \
+    LBM_CU_CASE(NS_VAL, 40, CALL)             \
     default:                                  \
       return hipErrorInvalidValue;            \
   }
@@ -1117,10 +1147,10 @@ constexpr size_t lds_for_blocks(int blocks) { return (size_t)(160 * 1024) / (blo
 
 template <int Q, int ST, int LAY, int CU>
 constexpr size_t step_lds() {
-  constexpr bool fp32 = (ST == ST_FP32 || ST == ST_FP32_DEV) && (CU == 0 || (CU & 4));
+  constexpr bool fp32 = (ST == ST_FP32 || ST == ST_FP32_DEV) && ((CU & 7) == 0 || (CU & 4));
   if constexpr (Q == 27 && fp32) return lds_for_blocks(2);
   if constexpr (Q == 9 && fp32 && LAY == LAY_AB) return lds_for_blocks(3);
-  if constexpr (Q == 9 && ST == ST_FP64 && LAY == LAY_AB && (CU == 0 || (CU & 4))) return lds_for_blocks(2);
+  if constexpr (Q == 9 && ST == ST_FP64 && LAY == LAY_AB && ((CU & 7) == 0 || (CU & 4))) return lds_for_blocks(2);
   return 0;
 }
 
