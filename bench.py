@@ -300,7 +300,7 @@ def main():
     ap.add_argument("--storage", default="fp32")
     ap.add_argument("--stream", default="aa", choices=["aa", "ab"],
                     help="population layout: in place (aa, measured faster for D2Q9 FP32) or two arrays (ab)")
-    ap.add_argument("--cpu-steps", type=int, default=7)
+    ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-cpu-single", action="store_true", help="skip the single-thread oracle step")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP16, D3Q27 and adjoint legs")
