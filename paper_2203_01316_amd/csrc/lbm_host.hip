@@ -579,6 +579,9 @@ static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   else
     a.tilemap = ctx->lay() == LAY_AA_N ? 2 : 0;
   a.row_blocks = 2 * ((ctx->p.nx + 255) / 256);
+  // the swapped in-place phase of a lattice without geometry whose x-rows
+  // are whole blocks realigns its x-pushes through LDS (k_bulk XR)
+  a.xr = !ctx->geom && ctx->p.storage != LBM_FP64 && ctx->p.nx % 256 == 0;
   for (int k = 0; k < 27; k++) {
     a.sf[k] = ctx->sfc[k];
     a.sh[k] = ctx->shc[k];

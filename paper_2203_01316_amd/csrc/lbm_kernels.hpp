@@ -105,6 +105,8 @@ struct KArgs {
   int32_t tilemap;         // block -> tile order: 0 one slab per XCD, 1 chunks per XCD,
                            // 2 dispatch order
   int32_t row_blocks;      // consecutive blocks per XCD chunk (tilemap 1)
+  int32_t xr;              // swapped in-place phase without geometry: the x-pushes
+                           // go through LDS (needs nx % 256 == 0)
   double sf[27];           // rates of f, chimera order
   double sh[27];           // rates of h, chimera order
   float sf32[27];          // the same rates rounded for FP32 arithmetic
