@@ -170,6 +170,73 @@ __device__ __forceinline__ void to_central(R *g, R ux, R uy, R uz) {
   }
 }
 
+// The same transform in two stages: raw moments first (k0 = a + b + c,
+// k1 = c - a, k2 = c + a per axis), whose zeroth and first orders give rho and
+// the momentum, then the shift of each axis to central moments about u
+// (k1 - u k0, k2 - 2 u k1 + u^2 k0).  Both stages together cost what the
+// direct transform costs, and the velocity needs no separate sums.
+template <class R>
+__device__ __forceinline__ void raw3(R &a, R &b, R &c) {
+  const R k0 = a + b + c;
+  const R k1 = c - a;
+  const R k2 = c + a;
+  a = k0;
+  b = k1;
+  c = k2;
+}
+
+template <class R>
+__device__ __forceinline__ void shift3(R &a, R &b, R &c, R u) {
+  const R k1 = b - u * a;
+  const R k2 = c - R(2) * u * b + u * u * a;
+  b = k1;
+  c = k2;
+}
+
+template <int D, class R>
+__device__ __forceinline__ void to_raw(R *g) {
+  if constexpr (D == 2) {
+#pragma unroll
+    for (int cx = 0; cx < 3; cx++) raw3(g[cx * 3 + 0], g[cx * 3 + 1], g[cx * 3 + 2]);
+#pragma unroll
+    for (int my = 0; my < 3; my++) raw3(g[0 + my], g[3 + my], g[6 + my]);
+  } else {
+#pragma unroll
+    for (int cxy = 0; cxy < 9; cxy++) raw3(g[cxy * 3 + 0], g[cxy * 3 + 1], g[cxy * 3 + 2]);
+#pragma unroll
+    for (int cx = 0; cx < 3; cx++)
+#pragma unroll
+      for (int mz = 0; mz < 3; mz++) raw3(g[cx * 9 + 0 + mz], g[cx * 9 + 3 + mz], g[cx * 9 + 6 + mz]);
+#pragma unroll
+    for (int myz = 0; myz < 9; myz++) raw3(g[myz], g[9 + myz], g[18 + myz]);
+  }
+}
+
+template <int D, class R>
+__device__ __forceinline__ void raw_to_central(R *g, R ux, R uy, R uz) {
+  if constexpr (D == 2) {
+#pragma unroll
+    for (int mx = 0; mx < 3; mx++) shift3(g[mx * 3 + 0], g[mx * 3 + 1], g[mx * 3 + 2], uy);
+#pragma unroll
+    for (int my = 0; my < 3; my++) shift3(g[0 + my], g[3 + my], g[6 + my], ux);
+  } else {
+#pragma unroll
+    for (int mxy = 0; mxy < 9; mxy++) shift3(g[mxy * 3 + 0], g[mxy * 3 + 1], g[mxy * 3 + 2], uz);
+#pragma unroll
+    for (int mx = 0; mx < 3; mx++)
+#pragma unroll
+      for (int mz = 0; mz < 3; mz++) shift3(g[mx * 9 + 0 + mz], g[mx * 9 + 3 + mz], g[mx * 9 + 6 + mz], uy);
+#pragma unroll
+    for (int myz = 0; myz < 9; myz++) shift3(g[myz], g[9 + myz], g[18 + myz], ux);
+  }
+}
+
+// Chimera slots of the first-order moments 100, 010 (and 001).
+template <int D>
+__host__ __device__ constexpr int first_order_slot(int d) {
+  return D == 2 ? (d == 0 ? 3 : 1) : (d == 0 ? 9 : (d == 1 ? 3 : 1));
+}
+
 template <int D, class R>
 __device__ __forceinline__ void from_central(R *g, R ux, R uy, R uz) {
   if constexpr (D == 2) {
@@ -336,6 +403,22 @@ __device__ __forceinline__ void collide(R *g, const R *s, R ux, R uy, R uz, R sr
   to_central<D, R>(g, ux, uy, uz);
   const R psi = g[0] + R(0.5) * src;
   relax<D, R, TR, ONE>(g, s, psi, src, db);
+  from_central<D, R>(g, ux, uy, uz);
+}
+
+// The same collision for the hydrodynamic lattice, whose velocity comes from
+// its own moments: rho and u are read off the raw moments, which are then
+// shifted to central moments (source-free).
+template <int D, class R, bool TR = false, int ONE = RATE1_NONE>
+__device__ __forceinline__ void collide_own_u(R *g, const R *s, R &rho, R &ux, R &uy, R &uz, R db = R(0)) {
+  to_raw<D, R>(g);
+  rho = g[0];
+  const R inv = R(1) / rho;
+  ux = g[first_order_slot<D>(0)] * inv;
+  uy = g[first_order_slot<D>(1)] * inv;
+  uz = D == 3 ? g[first_order_slot<D>(2)] * inv : R(0);
+  raw_to_central<D, R>(g, ux, uy, uz);
+  relax<D, R, TR, ONE>(g, s, g[0], R(0), db);
   from_central<D, R>(g, ux, uy, uz);
 }
 

@@ -187,10 +187,12 @@ Layout layout(const lbm_params *p) {
   const int Q = p->lattice;
   size_t off = 0;
   // One region per copy holds every stored lattice (lbm_impl.hpp): tiles of
-  // consecutive nodes with the Q slots of f then of h (FP64/FP32), or Q planes
-  // of plane_nodes() elements per lattice (FP16).
+  // consecutive nodes with the Q slots of f then of h (FP64/FP32), tiles of
+  // (f, h) pairs (FP16 with both lattices: h starts one element after f), or
+  // Q planes of plane_nodes() elements (FP16, h only).
   const size_t es = storage_size(p->storage);
-  const bool planes = p->storage == LBM_FP16_DEV;
+  const bool fp16 = p->storage == LBM_FP16_DEV;
+  const bool planes = fp16 && !p->with_ns;
   const int nlat = p->with_ns ? 2 : 1;
   L.pop_bytes = align_up((size_t)Q * plane_nodes(n, Q) * es);
   L.region_bytes = (size_t)nlat * L.pop_bytes;
@@ -199,7 +201,7 @@ Layout layout(const lbm_params *p) {
   for (int c = 0; c < 2; c++) {
     L.off_region[c] = c < copies ? off : L.off_region[0];
     if (c < copies) off += L.region_bytes;
-    const size_t h_at = !p->with_ns ? 0 : planes ? L.pop_bytes : (size_t)Q * (pop_tile_bytes(Q) / es) * es;
+    const size_t h_at = !p->with_ns ? 0 : fp16 ? es : (size_t)Q * (pop_tile_bytes(Q) / es) * es;
     L.off_pop[0][c] = L.off_region[c];
     L.off_pop[1][c] = L.off_region[c] + h_at;
   }
@@ -570,8 +572,8 @@ static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   // place (AA), chunks of two x-rows per XCD with two arrays (AB); D2Q9 FP16
   // planes one slab per XCD (dispatch order in the streamed AA phase); D3Q27
   // tiles dispatch order (the orders measured within 1% of each other);
-  // D3Q27 FP16 planes chunks of two x-rows per XCD
-  const bool planes = ctx->p.storage == LBM_FP16_DEV;
+  // D3Q27 FP16 planes chunks of two x-rows per XCD.  FP16 pairs are tiles.
+  const bool planes = ctx->p.storage == LBM_FP16_DEV && !ctx->p.with_ns;
   if (ctx->Q == 27)
     a.tilemap = planes ? 1 : 2;
   else if (!planes)
@@ -582,6 +584,8 @@ static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   // the swapped in-place phase of a lattice without geometry whose x-rows
   // are whole blocks realigns its x-pushes through LDS (k_bulk XR)
   a.xr = !ctx->geom && ctx->p.storage != LBM_FP64 && ctx->p.nx % 256 == 0;
+  // FP16 pairs address a byte offset of up to 4 Q (padded nodes) per slot base
+  a.pair64 = (double)4 * ctx->Q * (double)plane_nodes(ctx->n, ctx->Q) >= 4294967296.0;
   for (int k = 0; k < 27; k++) {
     a.sf[k] = ctx->sfc[k];
     a.sh[k] = ctx->shc[k];

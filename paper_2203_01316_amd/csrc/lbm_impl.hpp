@@ -75,8 +75,19 @@ struct StT<ST_FP16_DEV> {
 // per tile.  A block then reads and writes runs of consecutive bytes per slot
 // and tile, and all slots of a tile share DRAM pages.  Inside a tile the slots
 // of equal (e_z, e_y), which are pulled from one neighbouring row, are
-// adjacent.  FP16 elements: one plane of ps elements per slot and lattice,
-// [slot][m], which measured faster for 2-byte elements on MI355X.
+// adjacent.  FP16 elements with both lattices ("pairs"): the f and h values
+// of one slot and node sit side by side in a 4-byte element, and those
+// elements take the tile layout above with one lattice per tile, [m / T]
+// [tile_pos(slot)][m % T][f, h] with T = pop_tile_bytes(Q) / 4, so the buffer
+// of h starts one 2-byte element after that of f.  A step then moves both
+// lattices of a slot with one 4-byte access per node.  On MI355X the same
+// pulls over 54 2-byte planes reached 5.5 TB/s in a plain probe at 256^3, as
+// 4-byte pairs in planes 5.6 TB/s and as pairs in tiles 6.0 TB/s.  FP16
+// elements of one lattice: one plane of ps elements per slot, [slot][m].
+template <class S, int NL>
+__host__ __device__ constexpr bool fp16_pairs() {
+  return sizeof(S) == 2 && NL == 2;
+}
 template <int Q>
 __device__ __forceinline__ constexpr int tile_pos(int s) {
   return ((Lat<Q>::ez(s) + 1) * 3 + (Lat<Q>::ey(s) + 1)) * 3 + (Lat<Q>::ex(s) + 1) - (Lat<Q>::D == 2 ? 9 : 0);
@@ -92,15 +103,18 @@ __device__ __forceinline__ constexpr int dir_at_pos(int k) {
 }
 
 // NL: lattices per tile (1 or 2) when the caller knows it at compile time,
-// else 0 and ps holds the slots per tile.  A population's element index is
+// else 0 and ps holds the slots per tile (FP16 callers always know it).  A
+// population's element index is
 // slot_offset(slot) + node_offset(m): the first is uniform over a wavefront
 // (it folds into the scalar base address), the second is shared by the slots
 // pulled from one node.  Node indices are below 2^31 (the host rejects larger
 // lattices), so (m / T) x (slots per tile) < 2^31 / 128 x 54 < 2^32 for every
 // tile (T >= 128 nodes, at most 54 slots).
-template <int Q, class S>
+template <int Q, class S, int NL>
 __device__ __forceinline__ int64_t slot_offset(int slot, int64_t ps) {
-  if constexpr (sizeof(S) == 2)
+  if constexpr (fp16_pairs<S, NL>())
+    return (int64_t)2 * tile_pos<Q>(slot) * (pop_tile_bytes(Q) / 4);
+  else if constexpr (sizeof(S) == 2)
     return (int64_t)slot * ps;
   else
     return (int64_t)tile_pos<Q>(slot) * (pop_tile_bytes(Q) / (int)sizeof(S));
@@ -109,7 +123,10 @@ __device__ __forceinline__ int64_t slot_offset(int slot, int64_t ps) {
 template <int Q, class S, int NL>
 __device__ __forceinline__ uint64_t node_offset(int64_t ps, int64_t m) {
   const uint32_t u = (uint32_t)m;
-  if constexpr (sizeof(S) == 2) {
+  if constexpr (fp16_pairs<S, NL>()) {
+    constexpr uint32_t T = pop_tile_bytes(Q) / 4;
+    return 2 * ((uint64_t)u + (uint64_t)(u / T) * ((Q - 1) * T));
+  } else if constexpr (sizeof(S) == 2) {
     return u;
   } else {
     constexpr uint32_t T = pop_tile_bytes(Q) / sizeof(S);
@@ -145,9 +162,9 @@ __device__ __forceinline__ global_ptr<E> uniform_base(E *p) {
 // the access is a scalar plane base plus one zero-extended 32-bit lane offset,
 // which the pulls of both lattices from one node share (the scalar-base form
 // of the global loads and stores); wider elements use 64-bit offsets.
-template <class S, class P>
+template <class S, int NL, class P>
 __device__ __forceinline__ P elem_at(P p, uint64_t off) {
-  if constexpr (sizeof(S) == 2) {
+  if constexpr (sizeof(S) == 2 && !fp16_pairs<S, NL>()) {
     using C = typename std::conditional<std::is_const<typename std::remove_pointer<P>::type>::value,
                                         __attribute__((address_space(1))) const char,
                                         __attribute__((address_space(1))) char>::type;
@@ -164,8 +181,8 @@ __device__ __forceinline__ typename StT<ST>::R ldp(const void *base, int slot, i
   using T = StT<ST>;
   using R = typename T::R;
   const global_ptr<const typename T::S> p =
-      uniform_base(static_cast<const typename T::S *>(base) + slot_offset<Q, typename T::S>(slot, ps));
-  R v = StoreT<typename T::S>::ld(elem_at<typename T::S>(p, node_offset<Q, typename T::S, NL>(ps, m)));
+      uniform_base(static_cast<const typename T::S *>(base) + slot_offset<Q, typename T::S, NL>(slot, ps));
+  R v = StoreT<typename T::S>::ld(elem_at<typename T::S, NL>(p, node_offset<Q, typename T::S, NL>(ps, m)));
   if constexpr (T::DEV) v += weight<Q, R>(slot) * ref;
   return v;
 }
@@ -176,8 +193,58 @@ __device__ __forceinline__ void stp(void *base, int slot, int64_t ps, int64_t m,
   using T = StT<ST>;
   if constexpr (T::DEV) v -= weight<Q, typename T::R>(slot) * ref;
   const global_ptr<typename T::S> p =
-      uniform_base(static_cast<typename T::S *>(base) + slot_offset<Q, typename T::S>(slot, ps));
-  StoreT<typename T::S>::st(elem_at<typename T::S>(p, node_offset<Q, typename T::S, NL>(ps, m)), v);
+      uniform_base(static_cast<typename T::S *>(base) + slot_offset<Q, typename T::S, NL>(slot, ps));
+  StoreT<typename T::S>::st(elem_at<typename T::S, NL>(p, node_offset<Q, typename T::S, NL>(ps, m)), v);
+}
+
+// FP16 pairs: both lattices of slot `slot` of node m with one 4-byte access
+// at the f element (the h element is the next one).  With T = 2^k nodes per
+// tile the pair of node u sits 4 (u + (u / T)(Q - 1) T) bytes after the
+// slot's first element; W64 = false computes that in 32 bits (the host picks
+// it when 4 Q n < 2^32), so the access is a scalar slot base plus a 32-bit
+// lane offset.
+typedef _Float16 hpair __attribute__((ext_vector_type(2)));
+
+template <int Q>
+__host__ __device__ constexpr int pair_tile_log2() {
+  int k = 0;
+  while ((1 << (k + 1)) <= pop_tile_bytes(Q) / 4) k++;
+  return k;
+}
+static_assert((1 << pair_tile_log2<9>()) == pop_tile_bytes(9) / 4, "pair tiles must be powers of two");
+static_assert((1 << pair_tile_log2<27>()) == pop_tile_bytes(27) / 4, "pair tiles must be powers of two");
+
+template <int Q, bool W64>
+__device__ __forceinline__ uint64_t pair_byte_off(uint32_t u) {
+  constexpr int LT = pair_tile_log2<Q>();
+  constexpr uint32_t C = 4u * (Q - 1) * (1u << LT);
+  if constexpr (W64)
+    return ((uint64_t)u << 2) + (uint64_t)(u >> LT) * C;
+  else
+    return (uint64_t)((u << 2) + (u >> LT) * C);
+}
+
+template <int Q>
+__device__ __forceinline__ const char *pair_slot_base(const void *fbase, int slot) {
+  return static_cast<const char *>(fbase) + (size_t)4 * tile_pos<Q>(slot) * (pop_tile_bytes(Q) / 4);
+}
+
+template <int Q, bool W64>
+__device__ __forceinline__ void ldp_pair(const void *fbase, int slot, int64_t m, float fref, float href, float &f,
+                                         float &h) {
+  const global_ptr<const char> p = uniform_base(pair_slot_base<Q>(fbase, slot));
+  const hpair w = *reinterpret_cast<const __attribute__((address_space(1))) hpair *>(p + pair_byte_off<Q, W64>((uint32_t)m));
+  f = (float)w.x + weight<Q, float>(slot) * fref;
+  h = (float)w.y + weight<Q, float>(slot) * href;
+}
+
+template <int Q, bool W64>
+__device__ __forceinline__ void stp_pair(void *fbase, int slot, int64_t m, float f, float h, float fref, float href) {
+  const global_ptr<char> p = uniform_base(const_cast<char *>(pair_slot_base<Q>(fbase, slot)));
+  hpair w;
+  w.x = (_Float16)(f - weight<Q, float>(slot) * fref);
+  w.y = (_Float16)(h - weight<Q, float>(slot) * href);
+  __builtin_nontemporal_store(w, reinterpret_cast<__attribute__((address_space(1))) hpair *>(p + pair_byte_off<Q, W64>((uint32_t)m)));
 }
 
 // Value a store followed by a load of population i would return.
@@ -425,6 +492,21 @@ __device__ __forceinline__ void xr_put(int lat, int i, R v) {
   xr_lds<R>()[(lat * xr_dirs<Q>() + xr_index<Q>(i)) * 256 + threadIdx.x] = v;
 }
 
+template <int Q, bool W64>
+__device__ __forceinline__ void xr_pair_stores(const KArgs &a, const Node &c, const float *lds, int sp, int sm,
+                                               uint32_t xp, uint32_t xm) {
+#pragma unroll
+  for (int k = 0; k < Q; k++) {
+    const int i = dir_at_pos<Q>(k);
+    if (Lat<Q>::ex(i) == 0) continue;
+    const int s = Lat<Q>::ex(i) > 0 ? sp : sm;
+    uint32_t node = (Lat<Q>::ex(i) > 0 ? xp : xm) + c.Y[1 + Lat<Q>::ey(i)];
+    if constexpr (Lat<Q>::D == 3) node += c.Z[1 + Lat<Q>::ez(i)];
+    stp_pair<Q, W64>(a.fdst, i, (int64_t)node, lds[xr_index<Q>(i) * 256 + s],
+                     lds[(xr_dirs<Q>() + xr_index<Q>(i)) * 256 + s], float(a.fref), float(a.href));
+  }
+}
+
 // After both lattices are handed over: one barrier, then each thread stores
 // the pushes of its source threads (slot i, node x_s + e_i), in the tile's
 // address order.
@@ -440,6 +522,14 @@ __device__ __forceinline__ void xr_store(const KArgs &a, const Node &c) {
   uint32_t xp = x0 + (uint32_t)sp + 1u;
   if (xp >= nx) xp -= nx;
   const uint32_t xm = (x0 + (uint32_t)sm == 0u) ? nx - 1u : x0 + (uint32_t)sm - 1u;
+  if constexpr (NS && ST == ST_FP16_DEV) {
+    // FP16 pairs: f and h of a slot in one store
+    if (a.pair64)
+      xr_pair_stores<Q, true>(a, c, lds, sp, sm, xp, xm);
+    else
+      xr_pair_stores<Q, false>(a, c, lds, sp, sm, xp, xm);
+    return;
+  }
 #pragma unroll
   for (int lat = NS ? 0 : 1; lat < 2; lat++) {
 #pragma unroll
@@ -455,6 +545,32 @@ __device__ __forceinline__ void xr_store(const KArgs &a, const Node &c) {
   }
 }
 
+// Pulls and stores of FP16 pairs (both lattices), in the tile's address
+// order; XR leaves the x-pushes to xr_store.
+template <int Q, int LAY, bool W64>
+__device__ __forceinline__ void pair_loads(const KArgs &a, const Node &c, int64_t m, float *f, float *h) {
+#pragma unroll
+  for (int k = 0; k < Q; k++) {
+    const int i = dir_at_pos<Q>(k);
+    int sl;
+    int64_t nd;
+    pull_addr<Q, LAY>(a, c, m, i, sl, nd);
+    ldp_pair<Q, W64>(a.fsrc, sl, nd, float(a.fref), float(a.href), f[i], h[i]);
+  }
+}
+template <int Q, int LAY, bool XR, bool W64>
+__device__ __forceinline__ void pair_stores(const KArgs &a, const Node &c, int64_t m, const float *f, const float *h) {
+#pragma unroll
+  for (int k = 0; k < Q; k++) {
+    const int i = dir_at_pos<Q>(k);
+    if (XR && Lat<Q>::ex(i) != 0) continue;
+    int sl;
+    int64_t nd;
+    store_addr<Q, LAY>(a, c, m, i, sl, nd);
+    stp_pair<Q, W64>(a.fdst, sl, nd, f[i], h[i], float(a.fref), float(a.href));
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Epilogue: pre-collision populations f, h (direction order) of node m ->
 // collide and store (f, h then hold the stored post-collision values), or
@@ -466,15 +582,19 @@ __device__ __forceinline__ void xr_store(const KArgs &a, const Node &c) {
 // so their transform is skipped (the Cumulants-1st and hydrodynamic presets).
 // XR: the swapped in-place phase's x-pushes go through LDS (xr_store; the
 // whole block must reach it).
+// FP16 pairs store f and h of a slot together once both are collided.
 template <int Q, int ST, bool NS, int MODE, int LAY, int CU = 0, bool XR = false>
 __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, typename StT<ST>::R *f,
                                             typename StT<ST>::R *h) {
   using R = typename StT<ST>::R;
   constexpr int D = Lat<Q>::D;
-  R rho = 0, ux, uy, uz;
-  if constexpr (NS)
+  constexpr bool PR = NS && ST == ST_FP16_DEV;
+  // a central-moment f step takes rho and u from its own transform
+  constexpr bool OWN_U = NS && MODE == MODE_STEP && !(CU & 2);
+  R rho = 0, ux = 0, uy = 0, uz = 0;
+  if constexpr (NS && !OWN_U)
     velocity_dir<Q, R>(f, rho, ux, uy, uz);
-  else
+  else if constexpr (!NS)
     prescribed_u<Q, R>(a, m, ux, uy, uz);
   const R src = a.src ? static_cast<const R *>(a.src)[m] : R(0);
   if constexpr (MODE == MODE_STEP) {
@@ -487,8 +607,8 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
       else if constexpr (CU & 2)
         collide_cu<D, R, 0, true>(g, rates<R>(a, true), ux, uy, uz, R(0), bulk_delta<R>(a));
       else
-        collide<D, R, true, (CU & 8) ? RATE1_ORD3 : RATE1_NONE>(g, rates<R>(a, true), ux, uy, uz, R(0),
-                                                                 bulk_delta<R>(a));
+        collide_own_u<D, R, true, (CU & 8) ? RATE1_ORD3 : RATE1_NONE>(g, rates<R>(a, true), rho, ux, uy, uz,
+                                                                       bulk_delta<R>(a));
 #pragma unroll
       for (int k = 0; k < Q; k++) {
         const int i = split_order<Q, LAY, CU>() ? dir_at_pos<Q>(k) : k;
@@ -501,6 +621,7 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
             continue;
           }
         }
+        if constexpr (PR) continue;
         store_addr<Q, LAY>(a, c, m, i, sl, nd);
         stp<Q, ST, NS ? 2 : 1>(a.fdst, sl, a.ps, nd, f[i], R(a.fref));
       }
@@ -526,8 +647,15 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
           continue;
         }
       }
+      if constexpr (PR) continue;
       store_addr<Q, LAY>(a, c, m, i, sl, nd);
       stp<Q, ST, NS ? 2 : 1>(a.hdst, sl, a.ps, nd, h[i], R(a.href));
+    }
+    if constexpr (PR) {
+      if (a.pair64)
+        pair_stores<Q, LAY, XR, true>(a, c, m, f, h);
+      else
+        pair_stores<Q, LAY, XR, false>(a, c, m, f, h);
     }
     if constexpr (XR) {
       static_assert(LAY == LAY_AA_S, "realigned pushes belong to the swapped in-place phase");
@@ -653,7 +781,12 @@ __device__ __forceinline__ void bulk_node(const KArgs &a, int64_t m) {
   if constexpr (GEOM) cl = a.cls[m];
   const Node c = coords<Q>(a, m);
   R f[Q], h[Q];
-  if constexpr (split_order<Q, LAY, CU>()) {
+  if constexpr (NS && ST == ST_FP16_DEV) {
+    if (a.pair64)
+      pair_loads<Q, LAY, true>(a, c, m, f, h);
+    else
+      pair_loads<Q, LAY, false>(a, c, m, f, h);
+  } else if constexpr (split_order<Q, LAY, CU>()) {
     if constexpr (NS) {
 #pragma unroll
       for (int k = 0; k < Q; k++) {
@@ -980,7 +1113,7 @@ __global__ void __launch_bounds__(256) k_init(const InitArgs a) {
 // Stored post-collision state <-> FP64 [Q][n] (direction order).  Reading
 // out, solid nodes (cls) report zeros; writing in fills the layout's
 // post-collision addresses.
-template <int Q, int ST, int LAY, bool TO_STORAGE>
+template <int Q, int ST, int LAY, bool TO_STORAGE, int NL>
 __global__ void __launch_bounds__(256) k_convert(const KArgs a, const void *from, void *to, double ref) {
   using R = typename StT<ST>::R;
   const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -993,9 +1126,9 @@ __global__ void __launch_bounds__(256) k_convert(const KArgs a, const void *from
     int64_t nd;
     post_addr<Q, LAY>(a, c, m, i, sl, nd);
     if constexpr (TO_STORAGE)
-      stp<Q, ST>(to, sl, a.ps, nd, R(static_cast<const double *>(from)[i * a.n + m]), R(ref));
+      stp<Q, ST, NL>(to, sl, a.ps, nd, R(static_cast<const double *>(from)[i * a.n + m]), R(ref));
     else
-      static_cast<double *>(to)[i * a.n + m] = solid ? 0.0 : double(ldp<Q, ST>(from, sl, a.ps, nd, R(ref)));
+      static_cast<double *>(to)[i * a.n + m] = solid ? 0.0 : double(ldp<Q, ST, NL>(from, sl, a.ps, nd, R(ref)));
   }
 }
 
@@ -1307,12 +1440,22 @@ static hipError_t init_t(const InitArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// The lattice count of the layout comes from the arguments: f is set only
+// when both lattices are stored.
 template <int Q, int ST, int LAY>
 static hipError_t convert_t(bool to_storage, const KArgs &a, const void *from, void *to, double ref, hipStream_t s) {
-  if (to_storage)
-    k_convert<Q, ST, LAY, true><<<blocks_for(a.n, 256), 256, 0, s>>>(a, from, to, ref);
-  else
-    k_convert<Q, ST, LAY, false><<<blocks_for(a.n, 256), 256, 0, s>>>(a, from, to, ref);
+  const unsigned g = blocks_for(a.n, 256);
+  if (a.fsrc) {
+    if (to_storage)
+      k_convert<Q, ST, LAY, true, 2><<<g, 256, 0, s>>>(a, from, to, ref);
+    else
+      k_convert<Q, ST, LAY, false, 2><<<g, 256, 0, s>>>(a, from, to, ref);
+  } else {
+    if (to_storage)
+      k_convert<Q, ST, LAY, true, 1><<<g, 256, 0, s>>>(a, from, to, ref);
+    else
+      k_convert<Q, ST, LAY, false, 1><<<g, 256, 0, s>>>(a, from, to, ref);
+  }
   return hipGetLastError();
 }
 

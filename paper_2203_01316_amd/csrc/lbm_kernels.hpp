@@ -107,6 +107,7 @@ struct KArgs {
   int32_t row_blocks;      // consecutive blocks per XCD chunk (tilemap 1)
   int32_t xr;              // swapped in-place phase without geometry: the x-pushes
                            // go through LDS (needs nx % 256 == 0)
+  int32_t pair64;          // FP16 pairs: 64-bit lane offsets (4 Q n >= 2^32)
   double sf[27];           // rates of f, chimera order
   double sh[27];           // rates of h, chimera order
   float sf32[27];          // the same rates rounded for FP32 arithmetic
