@@ -125,7 +125,9 @@ def copy_ceiling(torch, L, dev, nbytes=2 << 30, reps=20):
 
 
 def time_steps(torch, g, steps, warmup):
-    """GPU seconds per step over `steps` back-to-back steps (events on the stream)."""
+    """GPU seconds per step over `steps` back-to-back steps (events on the stream).
+    The legs warm up for as many steps as they time: on MI355X the first few
+    hundred steps after a lattice is set up run up to 6% slower."""
     g.step(warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -146,7 +148,7 @@ def leg_cylinder(torch, L, W, np, storage, stream, nx, ny, steps, cu_f=False, cu
               relax_h="1st" if cu_h else "trt", cumulant_f=cu_f, cumulant_h=cu_h)
     g.set_velocity(uf)
     g.init(H0, u=uf.astype(np.float64), rho=rho0)
-    sec = time_steps(torch, g, steps, 50)
+    sec = time_steps(torch, g, steps, steps)
     bpn = 2 * 2 * 9 * (8 if storage == "fp64" else 2 if storage == "fp16_dev" else 4)
     mlups = nx * ny / sec / 1e6
     del g
@@ -165,7 +167,7 @@ def leg_tgv(torch, L, W, storage, n1, steps, cu=False, stream="ab"):
               stream=L.STREAM_AA if stream == "aa" else L.STREAM_AB)
     g.init(H, u=u, rho=rho)
     del rho, u, H
-    sec = time_steps(torch, g, steps, 10)
+    sec = time_steps(torch, g, steps, steps)
     red = g.reduce()
     bpn = 2 * 2 * 27 * (2 if storage == "fp16_dev" else 4)
     mlups = n1 ** 3 / sec / 1e6

@@ -1373,14 +1373,18 @@ static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b -
 // order-limited cumulant step 1192 at 2 against 1218 at 3 and 1244 at 4 (AA:
 // 1273 against 1326 at 3); at 2048^2 the D2Q9 two-array step takes 97.2 us
 // at 3 against 100.9, and with FP64 storage 196.1 at 2 against 203.5.  The
-// D2Q9 AA layout, FP16 storage, the FP64 D3Q27 steps and the full cumulant
-// transform measured no gain or a loss.  0 = no cap.
+// D2Q9 AA layout, the FP16 two-array steps, the FP64 D3Q27 steps and the full
+// cumulant transform measured no gain or a loss.  The in-place D3Q27 FP16
+// central-moment step takes 630 us at 3 blocks per CU in its streamed phase
+// against 646 uncapped (641 at 2, 632 at 4; the swapped phase holds 4 blocks
+// per CU through its LDS exchange).  0 = no cap.
 constexpr size_t lds_for_blocks(int blocks) { return (size_t)(160 * 1024) / (blocks + 1) + 1024; }
 
 template <int Q, int ST, int LAY, int CU>
 constexpr size_t step_lds() {
   constexpr bool fp32 = (ST == ST_FP32 || ST == ST_FP32_DEV) && ((CU & 7) == 0 || (CU & 4));
   if constexpr (Q == 27 && fp32) return lds_for_blocks(2);
+  if constexpr (Q == 27 && ST == ST_FP16_DEV && LAY == LAY_AA_N && (CU & 7) == 0) return lds_for_blocks(3);
   if constexpr (Q == 9 && fp32 && LAY == LAY_AB) return lds_for_blocks(3);
   if constexpr (Q == 9 && ST == ST_FP64 && LAY == LAY_AB && ((CU & 7) == 0 || (CU & 4))) return lds_for_blocks(2);
   return 0;

@@ -312,6 +312,58 @@ def test_d3q27_full_size_sampled(L, oracle, cu, stream):
     assert rel_l2(qh, oh) < TOL32
 
 
+@pytest.mark.parametrize("stream", ["ab", "aa"])
+def test_fp16_pairs_beyond_32bit_offsets(L, oracle, stream):
+    """FP16 deviation storage with both lattices on a 352^3 D3Q27 lattice,
+    whose (f, h) pairs lie up to 4.7 GB past a slot's base, beyond the reach
+    of 32-bit lane offsets: one GPU step equals the oracle's node collision
+    applied to the pulled neighbourhood on 2000 sampled nodes, half of them
+    among the nodes whose pairs lie more than 2^32 bytes past the slot base."""
+    import torch
+    n1 = 352
+    n = n1 ** 3
+    rho, u, H = W.taylor_green_3d(n1, 0.04)
+    g = L.LBM(27, n1, n1, n1, with_ns=True, storage="fp16_dev", nu=0.002, k=0.002, rho_ref=1.0, H_ref=1.0,
+              stream=L.STREAM_AA if stream == "aa" else L.STREAM_AB)
+    g.init(H, u=u, rho=rho)
+    del rho, u, H
+    g.step(3)
+    e, _, _ = oracle.lattice(27)
+    rng = np.random.default_rng(8)
+    # the pair of node m sits 4 (m + (m // 8192) 26 8192) bytes past its slot's base
+    far = np.nonzero(4 * (np.arange(n - 4 * 10 ** 6, n) + (np.arange(n - 4 * 10 ** 6, n) // 8192) * 26 * 8192)
+                     >= 2 ** 32)[0] + n - 4 * 10 ** 6
+    assert len(far) > 10 ** 6
+    nodes = np.concatenate([rng.choice(far, 1000, replace=False), rng.integers(0, n, 1000)])
+    x, y, z = nodes % n1, (nodes // n1) % n1, nodes // (n1 * n1)
+    src = (((x[None] - e[:, 0:1]) % n1) + n1 * (((y[None] - e[:, 1:2]) % n1)
+                                                 + n1 * ((z[None] - e[:, 2:3]) % n1)))
+    rows = torch.arange(27, device=g.device)[:, None]
+    srct = torch.as_tensor(src, device=g.device)
+    nt = torch.as_tensor(nodes, device=g.device)
+    pf = g.populations("f", "post")[rows, srct].cpu().numpy()
+    ph = g.populations("h", "post")[rows, srct].cpu().numpy()
+    torch.cuda.empty_cache()
+    g.step(1)
+    qf = g.populations("f", "post")[:, nt].cpu().numpy()
+    qh = g.populations("h", "post")[:, nt].cpu().numpy()
+    sf, sh = L.relaxation_rates(g.params)
+    sb = L.bulk_rate(g.params)
+    of = np.zeros_like(qf)
+    oh = np.zeros_like(qh)
+    for j in range(len(nodes)):
+        r = pf[:, j].sum()
+        uu = (e.T.astype(float) @ pf[:, j]) / r
+        of[:, j] = oracle.collide_node(27, pf[:, j], uu, sf, s_bulk=sb)
+        oh[:, j] = oracle.collide_node(27, ph[:, j], uu, sh)
+    ef, eh = rel_l2(qf, of), rel_l2(qh, oh)
+    ef_far, eh_far = rel_l2(qf[:, :1000], of[:, :1000]), rel_l2(qh[:, :1000], oh[:, :1000])
+    print(f"FP16 pairs 352^3 {stream}: f {ef:.2e} h {eh:.2e}; beyond 2^32 bytes f {ef_far:.2e} h {eh_far:.2e}")
+    # one step: the FP16 rounding of the stored deviations (2^-11 of deviations
+    # of a few per cent of the populations)
+    assert max(ef, eh, ef_far, eh_far) < 1e-4
+
+
 def test_largest_lattice_fp64(L, oracle):
     """A lattice of 32771 x 32765 nodes (1.07e9, population indices past 2^32),
     FP64, in-place layout.  The advection-diffusion step is linear and
