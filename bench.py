@@ -208,6 +208,23 @@ def leg_adjoint(torch, L, np, n1=512, steps=2000, interval=45):
         out[key] = {"forward_us_per_step": round((t1 - t0) / steps * 1e6, 2),
                     "backward_us_per_step": round((t2 - t1) / steps * 1e6, 2),
                     "ratio": round((t2 - t1) / (t1 - t0), 3)}
+    # an objective summed over every 10th step: the reverse sweep needs the
+    # residual of each observation time, recomputed by replaying the segments
+    from paper_2203_01316_amd.adjoint import tracking_objective
+    q = torch.tensor(src, dtype=torch.float32, device=g.device, requires_grad=True)
+    tracking_objective(q, g, H0, target, 20, 10, interval=5).backward()  # warm-up
+    q = torch.tensor(src, dtype=torch.float32, device=g.device, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = tracking_objective(q, g, H0, target, steps, 10, interval=interval)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out["tracking_every_10"] = {"forward_us_per_step": round((t1 - t0) / steps * 1e6, 2),
+                                "backward_us_per_step": round((t2 - t1) / steps * 1e6, 2),
+                                "ratio": round((t2 - t1) / (t1 - t0), 3)}
     # kernel-only ratio: step kernel vs adjoint kernel, events around each region
     g.set_source(src.astype(np.float32))
     g.init(H0)
@@ -429,6 +446,7 @@ def main():
         # checkpoints); without the replay alongside
         out["adjoint_forward_ratio"] = out["adjoint"]["with_replay"]["ratio"]
         out["adjoint_forward_ratio_no_replay"] = out["adjoint"]["no_replay"]["ratio"]
+        out["adjoint_forward_ratio_tracking"] = out["adjoint"]["tracking_every_10"]["ratio"]
     if not args.no_cpu:
         inputs = (flags, q, groups, uf.astype(np.float64), rho0, H0, nx, ny, nu, k)
         out["cpu_baseline"] = cpu_baseline(inputs, args.cpu_steps, not args.no_cpu_single)

@@ -337,6 +337,22 @@ lbm_status lbm_nusselt(lbm_ctx *ctx, int32_t group, int32_t x_in, int32_t x_out,
 lbm_status lbm_objective(lbm_ctx *ctx, const double *H_target_dev, void *lambda_dev, void *dJdQ_dev,
                          double *J);
 
+/* Objectives summed over several times (tracking H along the run): the two
+ * halves of lbm_objective.  lbm_objective_residual writes resid = H -
+ * H_target of the canonical state at the current time (zero at solid nodes)
+ * and returns its J = 1/2 sum resid^2 (synchronises); lbm_adjoint_seed turns a
+ * stored residual into the adjoint seed, lambda = resid in every direction and
+ * dJdQ = resid / 2, added to what the buffers hold when accumulate != 0 and
+ * written over it otherwise (lbm_objective = residual, then seed with
+ * accumulate = 0).  A reverse sweep adds the seed of time t after the reverse
+ * step that yields lambda at t; the residuals come from the forward states,
+ * which a checkpointed sweep recomputes segment by segment.  resid: device
+ * FP64 [n]; lambda, dJdQ as for lbm_objective.  Same contexts as the adjoint;
+ * LBM_EINVAL for NULL buffers. */
+lbm_status lbm_objective_residual(lbm_ctx *ctx, const double *H_target_dev, double *resid_dev, double *J);
+lbm_status lbm_adjoint_seed(lbm_ctx *ctx, const double *resid_dev, void *lambda_dev, void *dJdQ_dev,
+                            int32_t accumulate);
+
 /* One reverse step: lambda_next = dJ/d(state at t+1) -> lambda_prev =
  * dJ/d(state at t), and dJdQ += dJ/dQ through the collision of step t
  * (may be NULL).  The two lambda buffers must be distinct.  Uses only the

@@ -403,6 +403,31 @@ class Sim:
             lam = self.adjoint_step_dense(lam, dJdQ) if dense else self.adjoint_step(lam, dJdQ)
         return J, dJdQ
 
+    def gradient_source_tracking(self, H_target, steps, every, dense=False):
+        """J = sum over t = every, 2 every, ... <= steps of 1/2 sum (H_t - H*)^2
+        and dJ/dQ, from the current post state (the initial one): the forward
+        keeps the seed of every observation time, the reverse sweep adds the
+        seed of time t to lambda once a reverse step has carried lambda back
+        to t."""
+        seeds, J = {}, 0.0
+        for t in range(1, steps + 1):
+            self.step(1)
+            if t % every == 0:
+                Jt, lam_t, dq_t = self.objective(H_target)
+                J += Jt
+                seeds[t] = (lam_t, dq_t)
+        lam = np.zeros((self.Q, self.N))
+        dJdQ = np.zeros(self.N)
+        if steps in seeds:
+            lam += seeds[steps][0]
+            dJdQ += seeds[steps][1]
+        for t in range(steps - 1, -1, -1):
+            lam = self.adjoint_step_dense(lam, dJdQ) if dense else self.adjoint_step(lam, dJdQ)
+            if t in seeds:
+                lam = lam + seeds[t][0]
+                dJdQ += seeds[t][1]
+        return J, dJdQ
+
     def nusselt(self, group, x_in, x_out, k, T_wall, T_in):
         """(Nu, Nu from the heater flux alone, q_surface, q_in, q_out) of the
         canonical state at the current time (Sec. 4.4)."""

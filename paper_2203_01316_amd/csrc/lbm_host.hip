@@ -1165,6 +1165,47 @@ lbm_status lbm_objective(lbm_ctx *ctx, const double *H_target_dev, void *lambda_
   return LBM_OK;
 }
 
+lbm_status lbm_objective_residual(lbm_ctx *ctx, const double *H_target_dev, double *resid_dev, double *J) {
+  CTX_CHECK(ctx);
+  if (!H_target_dev || !resid_dev) {
+    set_err(&ctx->err, "H_target and resid must not be NULL");
+    return LBM_EINVAL;
+  }
+  if (lbm_status st = need_adjoint(ctx)) return st;
+  if (lbm_status st = need_ready(ctx)) return st;
+  if (lbm_status st = activate(ctx)) return st;
+  double *H = reinterpret_cast<double *>(ctx->ws + ctx->L.off_H);
+  double *sq = reinterpret_cast<double *>(ctx->ws + ctx->L.off_qx);
+  double *res = reinterpret_cast<double *>(ctx->ws + ctx->L.off_res);
+  KArgs a = make_args(ctx, ctx->cur);
+  a.out2 = H;
+  if (lbm_status st = run_pass(ctx, MODE_MACRO, a)) return st;
+  HIP_TRY(ctx, launch_resid(H, H_target_dev, a.cls, ctx->n, resid_dev, sq, ctx->stream), "residual kernel launch");
+  HIP_TRY(ctx, launch_reduce(nullptr, sq, nullptr, ctx->n, ctx->p.nx, ctx->p.ny, ctx->p.nz, nullptr, 0, nullptr,
+                             nullptr, 0, 0, reinterpret_cast<double *>(ctx->ws + ctx->L.off_part), kPartials, res,
+                             ctx->stream), "reduction launch");
+  double host[3];
+  HIP_TRY(ctx, hipMemcpyAsync(host, res, sizeof(host), hipMemcpyDeviceToHost, ctx->stream), "copy objective");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "objective");
+  if (J) *J = 0.5 * host[1];
+  return LBM_OK;
+}
+
+lbm_status lbm_adjoint_seed(lbm_ctx *ctx, const double *resid_dev, void *lambda_dev, void *dJdQ_dev,
+                            int32_t accumulate) {
+  CTX_CHECK(ctx);
+  if (!resid_dev || !lambda_dev || !dJdQ_dev) {
+    set_err(&ctx->err, "resid, lambda and dJdQ must not be NULL");
+    return LBM_EINVAL;
+  }
+  if (lbm_status st = need_adjoint(ctx)) return st;
+  if (lbm_status st = activate(ctx)) return st;
+  HIP_TRY(ctx, launch_seed_add(ctx->Q, ctx->p.storage == LBM_FP64, accumulate != 0, resid_dev, ctx->n, lambda_dev,
+                               static_cast<double *>(dJdQ_dev), ctx->stream),
+          "seed kernel launch");
+  return LBM_OK;
+}
+
 lbm_status lbm_adjoint_step(lbm_ctx *ctx, const void *lambda_next_dev, void *lambda_prev_dev, void *dJdQ_dev) {
   CTX_CHECK(ctx);
   if (!lambda_next_dev || !lambda_prev_dev || lambda_next_dev == lambda_prev_dev) {

@@ -75,6 +75,53 @@ hipError_t launch_seed(int Q, bool fp64, const double *H, const double *Ht, cons
 }
 
 // ---------------------------------------------------------------------------
+// Tracking objectives: residual and adjoint seed (one thread per node).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_resid(const double *H, const double *Ht, const uint8_t *cls, int64_t n,
+                                               double *d, double *sq) {
+  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (m >= n) return;
+  const double r = (cls && cls[m] == CLS_SOLID) ? 0.0 : H[m] - Ht[m];
+  d[m] = r;
+  sq[m] = r * r;
+}
+
+template <class R, bool ACC>
+__global__ void __launch_bounds__(256) k_seed_add(const double *d, int Q, int64_t n, R *lam, double *dJdQ) {
+  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (m >= n) return;
+  const double r = d[m];
+  for (int i = 0; i < Q; i++) {
+    R *p = lam + (int64_t)i * n + m;
+    *p = ACC ? *p + R(r) : R(r);
+  }
+  dJdQ[m] = ACC ? dJdQ[m] + 0.5 * r : 0.5 * r;
+}
+
+hipError_t launch_resid(const double *H, const double *Ht, const uint8_t *cls, int64_t n, double *d, double *sq,
+                        hipStream_t s) {
+  k_resid<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(H, Ht, cls, n, d, sq);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_add(int Q, bool fp64, bool accumulate, const double *d, int64_t n, void *lam, double *dJdQ,
+                           hipStream_t s) {
+  const unsigned g = (unsigned)((n + 255) / 256);
+  if (fp64) {
+    if (accumulate)
+      k_seed_add<double, true><<<g, 256, 0, s>>>(d, Q, n, static_cast<double *>(lam), dJdQ);
+    else
+      k_seed_add<double, false><<<g, 256, 0, s>>>(d, Q, n, static_cast<double *>(lam), dJdQ);
+  } else {
+    if (accumulate)
+      k_seed_add<float, true><<<g, 256, 0, s>>>(d, Q, n, static_cast<float *>(lam), dJdQ);
+    else
+      k_seed_add<float, false><<<g, 256, 0, s>>>(d, Q, n, static_cast<float *>(lam), dJdQ);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Deterministic FP64 reductions (fixed grid, fixed tree order).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double block_sum(double v, double *sh) {

@@ -165,5 +165,11 @@ hipError_t launch_adjoint(int Q, bool fp64, const KArgs &a, const void *lam_next
 // cls: node classes or null; solid nodes are left out of the objective.
 hipError_t launch_seed(int Q, bool fp64, const double *H, const double *Ht, const uint8_t *cls, int64_t n, void *lam,
                        void *dJdQ, double *sq, hipStream_t s);
+// Residual d = H - Ht (zero at solid nodes) and d^2 per node.
+hipError_t launch_resid(const double *H, const double *Ht, const uint8_t *cls, int64_t n, double *d, double *sq,
+                        hipStream_t s);
+// Adjoint seed from a residual: lam[i][m] (+)= d[m] for i < Q, dJdQ[m] (+)= d[m] / 2.
+hipError_t launch_seed_add(int Q, bool fp64, bool accumulate, const double *d, int64_t n, void *lam, double *dJdQ,
+                           hipStream_t s);
 
 }  // namespace lbm

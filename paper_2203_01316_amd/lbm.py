@@ -91,6 +91,8 @@ _sig = {
     "lbm_time": (C.c_int64, [_vp]),
     "lbm_sync": (C.c_int, [_vp]),
     "lbm_objective": (C.c_int, [_vp, _vp, _vp, _vp, _P(C.c_double)]),
+    "lbm_objective_residual": (C.c_int, [_vp, _vp, _vp, _P(C.c_double)]),
+    "lbm_adjoint_seed": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int32]),
     "lbm_adjoint_step": (C.c_int, [_vp, _vp, _vp, _vp]),
     "lbm_profile_begin": (C.c_int, [_vp, C.c_int32]),
     "lbm_profile_end": (C.c_int, [_vp, _P(C.c_double), _P(C.c_double), _P(C.c_int64)]),
@@ -398,6 +400,22 @@ class LBM:
         J = C.c_double()
         self._ck(_lib.lbm_objective(self.ctx, Ht.data_ptr(), lam.data_ptr(), dq.data_ptr(), C.byref(J)))
         return J.value, lam, dq
+
+    def objective_residual(self, H_target, resid=None):
+        """(J, resid): resid = H - H* of the canonical state (FP64 [n], zero at
+        solid nodes) and J = 1/2 sum resid^2."""
+        torch = self.torch
+        Ht = self._dev(H_target, torch.float64).reshape(self.n)
+        if resid is None:
+            resid = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        J = C.c_double()
+        self._ck(_lib.lbm_objective_residual(self.ctx, Ht.data_ptr(), resid.data_ptr(), C.byref(J)))
+        return J.value, resid
+
+    def adjoint_seed(self, resid, lam, dJdQ, accumulate=True):
+        """lam (+)= resid in every direction, dJdQ (+)= resid / 2."""
+        self._ck(_lib.lbm_adjoint_seed(self.ctx, resid.data_ptr(), lam.data_ptr(), dJdQ.data_ptr(),
+                                       1 if accumulate else 0))
 
     def adjoint_step(self, lam_next, lam_prev, dJdQ=None):
         """One reverse step into lam_prev; dJdQ (if given) accumulates."""

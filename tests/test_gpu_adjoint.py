@@ -217,6 +217,73 @@ def test_gradient_with_walls_matches_oracle(L, oracle):
     assert rel_l2(qt.grad.cpu().numpy(), go) < 1e-11
 
 
+@pytest.mark.parametrize("recompute,interval", [(True, 10), (True, 12), (False, 10)])
+def test_tracking_gradient_matches_oracle(L, oracle, recompute, interval):
+    """J summed every 7 steps over 150 steps on 48^2 (FP64) and dJ/dQ.  The
+    checkpointed sweep (snapshots every `interval` steps; the residual of each
+    observation time recomputed by replaying its segment, with observation
+    times on and off segment starts) and the sweep over stored residuals
+    both equal the oracle's reverse sweep."""
+    import torch
+    from paper_2203_01316_amd.adjoint import tracking_objective
+    n1, T, every = 48, 150, 7
+    n = n1 * n1
+    rng = np.random.default_rng(57)
+    src = 0.01 * rng.standard_normal(n)
+    target = 1.0 + 0.01 * rng.standard_normal(n)
+    H0 = np.ones(n)
+    g = _ctx(L, 9, (n1, n1, 1), "fp64", k=0.02)
+    q = torch.tensor(src, dtype=torch.float64, device=g.device, requires_grad=True)
+    J = tracking_objective(q, g, H0, target, T, every, interval=interval, recompute=recompute)
+    J.backward()
+    _, sh = L.relaxation_rates(g.params)
+    o = oracle.Sim(9, n1, n1, s_h=sh, u0=(0.03, 0.0, 0.0), src=src)
+    o.init(H0)
+    Jo, go = o.gradient_source_tracking(target, T, every)
+    assert float(J.detach()) == pytest.approx(Jo, rel=1e-12)
+    assert rel_l2(q.grad.cpu().numpy(), go) < 1e-11
+
+
+def test_tracking_gradient_with_walls_matches_oracle(L, oracle):
+    """The same objective (every 3 steps over 13, one target per time) on the
+    walled box against the oracle's dense reverse sweep."""
+    import torch
+    from paper_2203_01316_amd import workloads as W
+    from paper_2203_01316_amd.adjoint import tracking_objective
+    T, every = 13, 3
+    dims, flags, q, groups, u = _walls(W, "walled")
+    n = int(np.prod(dims))
+    rng = np.random.default_rng(58)
+    src = 0.01 * rng.standard_normal(n)
+    targets = [1.0 + 0.01 * rng.standard_normal(n) for _ in range(T // every)]
+    H0 = 1.0 + 0.1 * rng.uniform(size=n)
+    g = L.LBM(9, *dims, storage="fp64", k=0.02, with_source=True, u_mode=1, flags=flags, q=q, groups=groups)
+    g.set_velocity(u)
+    qt = torch.tensor(src, dtype=torch.float64, device=g.device, requires_grad=True)
+    J = tracking_objective(qt, g, H0, targets, T, every, interval=4)
+    J.backward()
+    _, sh = L.relaxation_rates(g.params)
+    o = oracle.Sim(9, *dims, s_h=sh, uvel=u, src=src, flags=flags, qlink=q, groups=groups)
+    o.init(H0)
+    # the oracle's sweep with one target per time, written out here
+    seeds, Jo = {}, 0.0
+    for t in range(1, T + 1):
+        o.step(1)
+        if t % every == 0:
+            Jt, lam_t, dq_t = o.objective(targets[t // every - 1])
+            Jo += Jt
+            seeds[t] = (lam_t, dq_t)
+    lam = np.zeros((9, n))
+    go = np.zeros(n)
+    for t in range(T - 1, -1, -1):
+        lam = o.adjoint_step_dense(lam, go)
+        if t in seeds:
+            lam = lam + seeds[t][0]
+            go += seeds[t][1]
+    assert float(J.detach()) == pytest.approx(Jo, rel=1e-12)
+    assert rel_l2(qt.grad.cpu().numpy(), go) < 1e-11
+
+
 def test_walls_gradient_vs_central_differences(L):
     """Walled box with a disc and EQ nodes, 96 x 48, 300 steps: the FP32
     adjoint gradient (checkpoints every 17 steps) matches FP64 central

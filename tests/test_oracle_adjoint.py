@@ -80,6 +80,49 @@ def test_adjoint_gradient_matches_central_differences(oracle):
     assert J > 0
 
 
+@pytest.mark.parametrize("every", [1, 4])
+def test_tracking_gradient_matches_central_differences(oracle, every):
+    """An objective summed over observation times (every `every` steps, the
+    last one at T or before it): the reverse sweep with the seed of each time
+    added once lambda is carried back to it equals central differences of J
+    (quadratic in Q, so exact up to rounding).  Seeds at the wrong time, or a
+    missing one, fail by O(1)."""
+    L, T = 8, 23
+    rng = np.random.default_rng(42 + every)
+    src = 0.01 * rng.standard_normal(L * L)
+    target = 1.0 + 0.01 * rng.standard_normal(L * L)
+    H0 = W.gaussian_hill(L, 2.0, 0.2, None, (0.0, 0.0), 0.0, 0.0)
+
+    def run(q):
+        sim, _ = _sim(oracle, L, src=q)
+        sim.init(H0)
+        return sim
+
+    def J_of(q):
+        sim = run(q)
+        J = 0.0
+        for t in range(1, T + 1):
+            sim.step(1)
+            if t % every == 0:
+                J += sim.objective(target)[0]
+        return J
+
+    J, g = run(src).gradient_source_tracking(target, T, every)
+    assert J == pytest.approx(J_of(src), rel=1e-14)
+    eps = 1e-3
+    for node in rng.integers(0, L * L, 6):
+        qp = src.copy()
+        qp[node] += eps
+        qm = src.copy()
+        qm[node] -= eps
+        fd = (J_of(qp) - J_of(qm)) / (2 * eps)
+        assert fd == pytest.approx(g[node], rel=1e-7, abs=1e-12)
+    # the final-state objective is the special case every = T
+    J1, g1 = run(src).gradient_source_tracking(target, T, T)
+    J2, g2 = run(src).gradient_source(target, T)
+    assert J1 == J2 and np.array_equal(g1, g2)
+
+
 @pytest.mark.parametrize("Q,L", [(9, 8), (27, 4)])
 def test_dense_adjoint_equals_periodic_adjoint(oracle, Q, L):
     """Two independent constructions of the periodic adjoint agree: the
