@@ -461,7 +461,12 @@ __device__ __forceinline__ constexpr bool split_order() {
 // 1250 us (central moments), 1274 -> 1250 us (cumulant pair), FP16 741 -> 714
 // us; 2048^2 D2Q9 coupled periodic FP32 96.5 -> 92.6 us, FP16 unchanged
 // (48 us).  Plain (cached) stores for the misaligned pushes instead gained
-// 1.5% on D2Q9 and nothing on D3Q27.
+// 1.5% on D2Q9 and nothing on D3Q27.  Lattices with geometry keep the plain
+// push: in the fused bulk-and-boundary kernel (142 VGPRs, 3 blocks per CU)
+// the realignment, with a flag per node for solid and listed nodes and its
+// barrier reached from converged control flow, was bit-identical but slowed
+// the 2048^2 heated-cylinder step from 92.5 to 95.2 us (cumulant pair 92.9 to
+// 99.9).
 // ---------------------------------------------------------------------------
 template <int Q>
 __device__ __forceinline__ constexpr int xr_index(int i) {
