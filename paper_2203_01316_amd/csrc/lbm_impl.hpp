@@ -868,7 +868,6 @@ template <int Q, int ST, bool NS, int LAY>
 __device__ __forceinline__ void pull_links(const KArgs &a, int64_t m, int32_t lb, uint32_t mask, int64_t side_node,
                                            typename StT<ST>::R *f, typename StT<ST>::R *h, double *flux) {
   using R = typename StT<ST>::R;
-  constexpr bool AB = LAY == LAY_AB;
   const Node c = coords<Q>(a, m);
   const R fref = R(a.fref), href = R(a.href);
 #pragma unroll
@@ -880,73 +879,79 @@ __device__ __forceinline__ void pull_links(const KArgs &a, int64_t m, int32_t lb
     h[i] = ldp<Q, ST, NS ? 2 : 1>(a.hsrc, sl, a.ps, nd, href);
   }
   if (mask == 0) return;
-  // g*_i(x_b) and g*_opp(i)(x_b) of step t-1 per link direction i: in AB the
-  // node's own stored values (all of f also give the wall velocity); in AA
-  // g*_i(x_b) at its post-collision address and g*_opp(i)(x_b) from the side
-  // buffer (its slot is rewritten by another node in this step)
-  const DevWall<R> *walls = static_cast<const DevWall<R> *>(a.walls);
-  R fbi[Q], fbo[Q], hbi[Q], hbo[Q];
-  DevWall<R> w[Q];
-  if constexpr (AB) {
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-      if constexpr (NS) fbi[i] = ldp<Q, ST, NS ? 2 : 1>(a.fsrc, i, a.ps, m, fref);
-      hbi[i] = ldp<Q, ST, NS ? 2 : 1>(a.hsrc, i, a.ps, m, href);
-    }
-  }
-#pragma unroll
-  for (int i = 1; i < Q; i++) {
-    if (!((mask >> i) & 1u)) continue;
-    const int32_t l = lb + __popc(mask & ((1u << i) - 1u));
-    w[i] = walls[l];
-    if constexpr (!AB) {
-      int sl;
-      int64_t nd;
-      post_addr<Q, LAY>(a, c, m, i, sl, nd);
-      if constexpr (NS) {
-        fbi[i] = ldp<Q, ST, NS ? 2 : 1>(a.fsrc, sl, a.ps, nd, fref);
-        fbo[i] = static_cast<const R *>(a.side_f)[l];
-      }
-      hbi[i] = ldp<Q, ST, NS ? 2 : 1>(a.hsrc, sl, a.ps, nd, href);
-      hbo[i] = static_cast<const R *>(a.side_h)[l];
-    }
-  }
-  // velocity of the boundary node for the wall equilibrium: momentum over
-  // density of its post-collision f of step t-1, or the prescribed velocity
-  R ux, uy, uz;
-  if constexpr (NS) {
-    if constexpr (AB) {
-      R rho;
-      velocity_dir<Q, R>(fbi, rho, ux, uy, uz);
-    } else {
+  if constexpr (LAY != LAY_AB) {
+    // AA: the boundary node's velocity at t-1 from the side buffer, then one
+    // link at a time (few registers: this path sets the register budget of
+    // the fused step kernel)
+    R ux, uy, uz;
+    if constexpr (NS) {
       const R *su = static_cast<const R *>(a.side_u) + 3 * side_node;
       ux = su[0];
       uy = su[1];
       uz = su[2];
+    } else {
+      prescribed_u<Q, R>(a, m, ux, uy, uz);
     }
+    const DevWall<R> *walls = static_cast<const DevWall<R> *>(a.walls);
+#pragma unroll
+    for (int i = 1; i < Q; i++) {
+      if (!((mask >> i) & 1u)) continue;
+      const int32_t l = lb + __popc(mask & ((1u << i) - 1u));
+      const DevWall<R> w = walls[l];
+      const int o = Lat<Q>::opp(i);
+      int sl;
+      int64_t nd;
+      post_addr<Q, LAY>(a, c, m, i, sl, nd);
+      // g*_i(x_b) at its post-collision address, g*_opp(i)(x_b) from the side
+      // buffer (its slot is rewritten by another node in this step)
+      if constexpr (NS) {
+        const R gbi = ldp<Q, ST, NS ? 2 : 1>(a.fsrc, sl, a.ps, nd, fref);
+        const R gbo = static_cast<const R *>(a.side_f)[l];
+        f[o] = (w.interp & 1) ? wall_ibb<R>(w.q, gbi, gbo, f[i]) : gbi;
+      }
+      const R gbi = ldp<Q, ST, NS ? 2 : 1>(a.hsrc, sl, a.ps, nd, href);
+      const R gbo = static_cast<const R *>(a.side_h)[l];
+      const R geq = geq_dir<Q, R>(i, w.H_w, ux, uy, uz);
+      h[o] = (w.interp & 2) ? wall_iabb<R>(w.q, gbi, gbo, h[i], geq) : -gbi + R(2) * geq;
+      if (flux) flux[l] = double(h[o]) - double(gbi);
+    }
+    return;
+  }
+  // AB: g*_i(x_b) and g*_opp(i)(x_b) of step t-1 are the node's own stored
+  // values; the wall velocity is the momentum over density of all of its f.
+  // One link at a time, as in AA.
+  R ux, uy, uz;
+  if constexpr (NS) {
+    R fb[Q], rho;
+#pragma unroll
+    for (int i = 0; i < Q; i++) fb[i] = ldp<Q, ST, NS ? 2 : 1>(a.fsrc, i, a.ps, m, fref);
+    velocity_dir<Q, R>(fb, rho, ux, uy, uz);
+    // the links reload their two values (from cache) instead of keeping all
+    // of f live in registers
+    asm volatile("" ::: "memory");
   } else {
     prescribed_u<Q, R>(a, m, ux, uy, uz);
   }
+  const DevWall<R> *walls = static_cast<const DevWall<R> *>(a.walls);
 #pragma unroll
   for (int i = 1; i < Q; i++) {
     if (!((mask >> i) & 1u)) continue;
+    const int32_t l = lb + __popc(mask & ((1u << i) - 1u));
+    const DevWall<R> w = walls[l];
     const int o = Lat<Q>::opp(i);
     // g*_i(x_f) is the pulled value f[i] / h[i] (never rewritten by another
     // link when it is used: that link would need x_f solid)
     if constexpr (NS) {
-      const R gbi = fbi[i], gbo = AB ? fbi[o] : fbo[i];
-      if (w[i].interp & 1)
-        f[o] = wall_ibb<R>(w[i].q, gbi, gbo, f[i]);
-      else
-        f[o] = gbi;  // bounce-back (Eq. IBB at q = 1/2)
+      const R gbi = ldp<Q, ST, NS ? 2 : 1>(a.fsrc, i, a.ps, m, fref);
+      const R gbo = ldp<Q, ST, NS ? 2 : 1>(a.fsrc, o, a.ps, m, fref);
+      f[o] = (w.interp & 1) ? wall_ibb<R>(w.q, gbi, gbo, f[i]) : gbi;  // else bounce-back (Eq. IBB at q = 1/2)
     }
-    const R gbi = hbi[i], gbo = AB ? hbi[o] : hbo[i];
-    const R geq = geq_dir<Q, R>(i, w[i].H_w, ux, uy, uz);
-    if (w[i].interp & 2)
-      h[o] = wall_iabb<R>(w[i].q, gbi, gbo, h[i], geq);
-    else
-      h[o] = -gbi + R(2) * geq;  // anti-bounce-back (Eq. IABB at q = 1/2)
-    if (flux) flux[lb + __popc(mask & ((1u << i) - 1u))] = double(h[o]) - double(gbi);
+    const R gbi = ldp<Q, ST, NS ? 2 : 1>(a.hsrc, i, a.ps, m, href);
+    const R gbo = ldp<Q, ST, NS ? 2 : 1>(a.hsrc, o, a.ps, m, href);
+    const R geq = geq_dir<Q, R>(i, w.H_w, ux, uy, uz);
+    // else anti-bounce-back (Eq. IABB at q = 1/2)
+    h[o] = (w.interp & 2) ? wall_iabb<R>(w.q, gbi, gbo, h[i], geq) : -gbi + R(2) * geq;
+    if (flux) flux[l] = double(h[o]) - double(gbi);
   }
 }
 
@@ -1377,9 +1382,9 @@ static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b -
 // us at 2 blocks per CU against 1235 uncapped (AA: 1266 against 1369), the
 // order-limited cumulant step 1192 at 2 against 1218 at 3 and 1244 at 4 (AA:
 // 1273 against 1326 at 3); at 2048^2 the D2Q9 two-array step takes 97.2 us
-// at 3 against 100.9, and with FP64 storage 196.1 at 2 against 203.5.  The
-// D2Q9 AA layout, the FP16 two-array steps, the FP64 D3Q27 steps and the full
-// cumulant transform measured no gain or a loss.  The in-place D3Q27 FP16
+// at 3 against 100.9, and with FP64 storage 196.1 at 2 against 203.5 (the
+// D2Q9 in-place fused step: fused_lds).  The FP16 two-array steps, the FP64
+// D3Q27 steps and the full cumulant transform measured no gain or a loss.  The in-place D3Q27 FP16
 // central-moment step takes 630 us at 3 blocks per CU in its streamed phase
 // against 646 uncapped (641 at 2, 632 at 4; the swapped phase holds 4 blocks
 // per CU through its LDS exchange).  0 = no cap.
@@ -1429,10 +1434,23 @@ static hipError_t special_t(int mode, int cu, const KArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// The fused D2Q9 step in place: FP32 at 3 blocks per CU in the swapped phase
+// and 4 in the streamed one.  With the one-link-at-a-time wall path (96 and
+// 70 VGPRs, where the swapped phase took 142 before) the uncapped 2048^2
+// heated-cylinder step ran 97.5 us, capped 92.5 (the cumulant pair 97.6 and
+// 93.3); FP16 runs fastest uncapped (48.0 us).
+template <int Q, int ST, int LAY, int CU>
+constexpr size_t fused_lds() {
+  constexpr bool fp32 = (ST == ST_FP32 || ST == ST_FP32_DEV) && ((CU & 7) == 0 || (CU & 4));
+  if constexpr (Q == 9 && fp32 && LAY == LAY_AA_S) return lds_for_blocks(3);
+  if constexpr (Q == 9 && fp32 && LAY == LAY_AA_N) return lds_for_blocks(4);
+  return step_lds<Q, ST, LAY, CU>();
+}
+
 template <int Q, int ST, bool NS, int LAY>
 static hipError_t fused_t(int cu, const KArgs &a, hipStream_t s) {
   const int sblocks = (int)((blocks_for(a.nspecial, 256) + 7) / 8 * 8);
-  LBM_DISPATCH_CU(NS, cu, (k_fused<Q, ST, NS, LAY, CU><<<blocks_for(a.n, 256) + sblocks, 256, step_lds<Q, ST, LAY, CU>(), s>>>(a, sblocks)))
+  LBM_DISPATCH_CU(NS, cu, (k_fused<Q, ST, NS, LAY, CU><<<blocks_for(a.n, 256) + sblocks, 256, fused_lds<Q, ST, LAY, CU>(), s>>>(a, sblocks)))
   return hipGetLastError();
 }
 
