@@ -130,6 +130,55 @@ def test_c5_gradient_vs_central_differences(L):
     assert big.sum() >= 8
 
 
+def test_tracking_gradient_fp32_vs_central_differences(L):
+    """512^2, 400 steps, the objective summed every 20 steps against one
+    target: the FP32 checkpointed sweep (snapshots every 20 steps, replayed
+    for the residuals) against FP64 central differences of the same objective
+    on 16 random nodes, with the bounds of the final-state test above."""
+    import torch
+    from paper_2203_01316_amd.adjoint import tracking_objective
+    n1, T, every, k = 512, 400, 20, 0.01
+    n = n1 * n1
+    src = 0.01 * np.random.Generator(np.random.PCG64(11)).standard_normal(n)
+    target = 1.0 + 0.01 * np.random.Generator(np.random.PCG64(12)).standard_normal(n)
+    nodes = np.random.Generator(np.random.PCG64(13)).choice(n, 16, replace=False)
+    H0 = np.ones(n)
+    g32 = _ctx(L, 9, (n1, n1, 1), "fp32", k=k)
+    q = torch.tensor(f32(src), dtype=torch.float32, device=g32.device, requires_grad=True)
+    J = tracking_objective(q, g32, H0, target, T, every, interval=20)
+    J.backward()
+    adj = q.grad.double().cpu().numpy()[nodes]
+    g64 = _ctx(L, 9, (n1, n1, 1), "fp64", k=k)
+    eps = 1e-3
+
+    def J64(qv):
+        g64.set_source(qv)
+        g64.init(H0)
+        Jv = 0.0
+        for _ in range(T // every):
+            g64.step(every)
+            Jv += g64.objective_residual(target)[0]
+        return Jv
+
+    fd = []
+    for m in nodes:
+        qp = src.copy()
+        qp[m] += eps
+        qm = src.copy()
+        qm[m] -= eps
+        fd.append((J64(qp) - J64(qm)) / (2 * eps))
+    fd = np.array(fd)
+    scale = np.abs(fd).max()
+    per_node = np.abs(adj - fd) / np.abs(fd)
+    big = np.abs(fd) >= 0.1 * scale
+    print("tracking gradient vs FD: max |adj - fd| / max |fd| %.2e, max relative on %d nodes %.2e"
+          % (np.abs(adj - fd).max() / scale, big.sum(), per_node[big].max()))
+    assert float(J.detach()) == pytest.approx(J64(src), rel=1e-4)
+    assert np.abs(adj - fd).max() < 1e-4 * scale, (adj, fd)
+    assert per_node[big].max() < 1e-4, (adj, fd)
+    assert big.sum() >= 8
+
+
 def _walls(W, case):
     if case == "walled":
         dims = (24, 14, 1)
