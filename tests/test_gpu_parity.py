@@ -312,18 +312,20 @@ def test_d3q27_full_size_sampled(L, oracle, cu, stream):
     assert rel_l2(qh, oh) < TOL32
 
 
-@pytest.mark.parametrize("stream", ["ab", "aa"])
-def test_fp16_pairs_beyond_32bit_offsets(L, oracle, stream):
-    """FP16 deviation storage with both lattices on a 352^3 D3Q27 lattice,
-    whose (f, h) pairs lie up to 4.7 GB past a slot's base, beyond the reach
-    of 32-bit lane offsets: one GPU step equals the oracle's node collision
-    applied to the pulled neighbourhood on 2000 sampled nodes, half of them
-    among the nodes whose pairs lie more than 2^32 bytes past the slot base."""
+@pytest.mark.parametrize("dims,stream", [((352, 352, 352), "ab"), ((352, 352, 352), "aa"), ((512, 512, 160), "aa")])
+def test_fp16_pairs_beyond_32bit_offsets(L, oracle, dims, stream):
+    """FP16 deviation storage with both lattices on D3Q27 lattices whose (f, h)
+    pairs lie up to 4.7 GB past a slot's base, beyond the reach of 32-bit lane
+    offsets (352^3; and 512 x 512 x 160 in place, whose rows of two blocks
+    also take the realigned pushes): one GPU step equals the oracle's node
+    collision applied to the pulled neighbourhood on 2000 sampled nodes, half
+    of them among the nodes whose pairs lie more than 2^32 bytes past the
+    slot base."""
     import torch
-    n1 = 352
-    n = n1 ** 3
-    rho, u, H = W.taylor_green_3d(n1, 0.04)
-    g = L.LBM(27, n1, n1, n1, with_ns=True, storage="fp16_dev", nu=0.002, k=0.002, rho_ref=1.0, H_ref=1.0,
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    rho, u, H = _taylor_green_box(nx, ny, nz, 0.04)
+    g = L.LBM(27, nx, ny, nz, with_ns=True, storage="fp16_dev", nu=0.002, k=0.002, rho_ref=1.0, H_ref=1.0,
               stream=L.STREAM_AA if stream == "aa" else L.STREAM_AB)
     g.init(H, u=u, rho=rho)
     del rho, u, H
@@ -335,9 +337,9 @@ def test_fp16_pairs_beyond_32bit_offsets(L, oracle, stream):
                      >= 2 ** 32)[0] + n - 4 * 10 ** 6
     assert len(far) > 10 ** 6
     nodes = np.concatenate([rng.choice(far, 1000, replace=False), rng.integers(0, n, 1000)])
-    x, y, z = nodes % n1, (nodes // n1) % n1, nodes // (n1 * n1)
-    src = (((x[None] - e[:, 0:1]) % n1) + n1 * (((y[None] - e[:, 1:2]) % n1)
-                                                 + n1 * ((z[None] - e[:, 2:3]) % n1)))
+    x, y, z = nodes % nx, (nodes // nx) % ny, nodes // (nx * ny)
+    src = (((x[None] - e[:, 0:1]) % nx) + nx * (((y[None] - e[:, 1:2]) % ny)
+                                                 + ny * ((z[None] - e[:, 2:3]) % nz)))
     rows = torch.arange(27, device=g.device)[:, None]
     srct = torch.as_tensor(src, device=g.device)
     nt = torch.as_tensor(nodes, device=g.device)
@@ -358,10 +360,28 @@ def test_fp16_pairs_beyond_32bit_offsets(L, oracle, stream):
         oh[:, j] = oracle.collide_node(27, ph[:, j], uu, sh)
     ef, eh = rel_l2(qf, of), rel_l2(qh, oh)
     ef_far, eh_far = rel_l2(qf[:, :1000], of[:, :1000]), rel_l2(qh[:, :1000], oh[:, :1000])
-    print(f"FP16 pairs 352^3 {stream}: f {ef:.2e} h {eh:.2e}; beyond 2^32 bytes f {ef_far:.2e} h {eh_far:.2e}")
+    print(f"FP16 pairs {dims} {stream}: f {ef:.2e} h {eh:.2e}; beyond 2^32 bytes f {ef_far:.2e} h {eh_far:.2e}")
     # one step: the FP16 rounding of the stored deviations (2^-11 of deviations
     # of a few per cent of the populations)
     assert max(ef, eh, ef_far, eh_far) < 1e-4
+
+
+def _taylor_green_box(nx, ny, nz, u0):
+    """The Taylor-Green vortex of workloads.taylor_green_3d on an nx x ny x nz
+    box (one period per axis)."""
+    if nx == ny == nz:
+        return W.taylor_green_3d(nx, u0)
+    x = 2 * np.pi * np.arange(nx) / nx
+    y = 2 * np.pi * np.arange(ny) / ny
+    z = 2 * np.pi * np.arange(nz) / nz
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    u = np.zeros((3, nx * ny * nz))
+    u[0] = (u0 * np.sin(X) * np.cos(Y) * np.cos(Z)).reshape(-1)
+    u[1] = (-u0 * np.cos(X) * np.sin(Y) * np.cos(Z)).reshape(-1)
+    p = (u0 * u0 / 16) * (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2)
+    rho = (1 + 3 * p).reshape(-1)
+    H = (1 + 0.1 * np.sin(X) * np.sin(Y) * np.sin(Z)).reshape(-1)
+    return rho, u, H
 
 
 def test_largest_lattice_fp64(L, oracle):
