@@ -1438,12 +1438,15 @@ static hipError_t special_t(int mode, int cu, const KArgs &a, hipStream_t s) {
 // and 4 in the streamed one.  With the one-link-at-a-time wall path (96 and
 // 70 VGPRs, where the swapped phase took 142 before) the uncapped 2048^2
 // heated-cylinder step ran 97.5 us, capped 92.5 (the cumulant pair 97.6 and
-// 93.3); FP16 runs fastest uncapped (48.0 us).
+// 93.3); FP16 runs fastest uncapped (48.0 us).  FP64 in place: 2 blocks per CU
+// in both phases, 218.5 us against 223.8 uncapped.
 template <int Q, int ST, int LAY, int CU>
 constexpr size_t fused_lds() {
-  constexpr bool fp32 = (ST == ST_FP32 || ST == ST_FP32_DEV) && ((CU & 7) == 0 || (CU & 4));
+  constexpr bool limited = (CU & 7) == 0 || (CU & 4);
+  constexpr bool fp32 = (ST == ST_FP32 || ST == ST_FP32_DEV) && limited;
   if constexpr (Q == 9 && fp32 && LAY == LAY_AA_S) return lds_for_blocks(3);
   if constexpr (Q == 9 && fp32 && LAY == LAY_AA_N) return lds_for_blocks(4);
+  if constexpr (Q == 9 && ST == ST_FP64 && limited && LAY != LAY_AB) return lds_for_blocks(2);
   return step_lds<Q, ST, LAY, CU>();
 }
 
