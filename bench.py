@@ -391,7 +391,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.storage != "fp64" else "f64",
+        "dtype": "f64" if args.storage in ("fp64", "fp32_sr") else "f32",
         "data": "synthetic",
         "config": {"workload": f"d2q9_ns_ade_heated_cylinder_{nx}x{ny}", "lattice": "D2Q9",
                    "lattices": "f (NS, CM) + h (ADE, CM-TRT)", "nx": nx, "ny": ny,
@@ -440,7 +440,11 @@ def main():
                        leg_cylinder(torch, L, W, np, "fp32", "aa", nx, ny, max(10, int(1000 * sc)), cu_f=True),
                        leg_cylinder(torch, L, W, np, "fp32", "aa", nx, ny, max(10, int(1000 * sc)), cu_f=True,
                                     cu_h=True),
-                       leg_tgv(torch, L, W, "fp32", 256, max(5, int(100 * sc)), cu=True)]
+                       leg_tgv(torch, L, W, "fp32", 256, max(5, int(100 * sc)), cu=True),
+                       # FP32 storage, FP64 arithmetic, stochastic rounding on store
+                       leg_cylinder(torch, L, W, np, "fp32_sr", "ab", nx, ny, max(10, int(1000 * sc))),
+                       leg_cylinder(torch, L, W, np, "fp32_sr", "aa", nx, ny, max(10, int(1000 * sc))),
+                       leg_tgv(torch, L, W, "fp32_sr", 256, max(5, int(100 * sc)))]
         out["adjoint"] = leg_adjoint(torch, L, np, steps=max(90, int(2000 * sc)))
         # headline: the checkpointed gradient with its forward replay (sqrt(T)
         # checkpoints); without the replay alongside

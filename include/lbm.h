@@ -65,10 +65,17 @@ typedef enum {
 
 typedef enum { LBM_D2Q9 = 9, LBM_D3Q27 = 27 } lbm_lattice;
 
-/* Storage type of the populations; arithmetic is FP64 for LBM_FP64 and FP32
- * otherwise.  The *_DEV types store deviations g_i - w_i g_ref from the rest
- * equilibrium of the reference values rho_ref / H_ref. */
-typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP32_DEV = 2, LBM_FP16_DEV = 3 } lbm_storage;
+/* Storage type of the populations; arithmetic is FP64 for LBM_FP64 and
+ * LBM_FP32_SR and FP32 otherwise.  The *_DEV types store deviations g_i - w_i
+ * g_ref from the rest equilibrium of the reference values rho_ref / H_ref.
+ * LBM_FP32_SR stores FP32 values rounded stochastically from the FP64 result:
+ * up or down to the two nearest FP32 values with probabilities set by the
+ * distance to each, drawn from a hash of the storage location and the step
+ * (deterministic for a given run).  A steady state then does not accumulate
+ * the bias that rounding to nearest repeats at every node and step; the
+ * in-place and two-array layouts round at different locations and agree to
+ * rounding, not bit for bit.  No adjoint. */
+typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP32_DEV = 2, LBM_FP16_DEV = 3, LBM_FP32_SR = 4 } lbm_storage;
 
 /* Streaming layout: two arrays (AB) or one array updated in place (AA). */
 typedef enum { LBM_STREAM_AB = 0, LBM_STREAM_AA = 1 } lbm_stream_mode;
@@ -237,7 +244,7 @@ lbm_status lbm_set_geometry(lbm_ctx *ctx, const uint16_t *flags, const double *q
 lbm_status lbm_get_links(lbm_ctx *ctx, lbm_link *out, int64_t cap, int64_t *count);
 
 /* Advection-only with u_mode = 1: borrowed per-node velocity field, device,
- * [3][n] in the arithmetic type (double for LBM_FP64, float otherwise).
+ * [3][n] in the arithmetic type (double for LBM_FP64 and LBM_FP32_SR, float otherwise).
  * With with_ns = 1 the field, when set, gives the velocity of EQ nodes. */
 lbm_status lbm_set_velocity(lbm_ctx *ctx, const void *u_dev);
 
@@ -326,7 +333,7 @@ lbm_status lbm_nusselt(lbm_ctx *ctx, int32_t group, int32_t x_in, int32_t x_out,
  * state.  Solid nodes carry no state: their lambda is ignored on input and
  * zero on output.
  * lambda: adjoint of the canonical (pre-collision) state, device [Q][n] in
- * the arithmetic type (double for LBM_FP64, float otherwise); dJdQ: device
+ * the arithmetic type (double for LBM_FP64 and LBM_FP32_SR, float otherwise); dJdQ: device
  * FP64 [n], an accumulator over all reverse steps. */
 
 /* Objective J = 1/2 sum_x (H(x) - H_target(x))^2 over the non-solid nodes of

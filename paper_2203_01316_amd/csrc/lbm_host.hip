@@ -79,11 +79,19 @@ size_t storage_size(int st) {
   switch (st) {
     case LBM_FP64: return 8;
     case LBM_FP32:
-    case LBM_FP32_DEV: return 4;
+    case LBM_FP32_DEV:
+    case LBM_FP32_SR: return 4;
     case LBM_FP16_DEV: return 2;
     default: return 0;
   }
 }
+
+// Arithmetic in FP64 (the storage types whose kernels compute in double).
+bool arith64(int st) { return st == LBM_FP64 || st == LBM_FP32_SR; }
+
+// Seed of the FP32_SR rounding draws of the writes made at time t: a new
+// draw per step (Fibonacci hashing of t).
+static uint32_t sr_seed(int64_t t) { return (uint32_t)((uint64_t)t * 0x9E3779B97F4A7C15ull >> 32); }
 
 bool set_err(std::string *dst, const char *fmt, ...) {
   char buf[512];
@@ -210,7 +218,7 @@ Layout layout(const lbm_params *p) {
   L.off_links = off;
   off += align_up(sizeof(DevLink) * (size_t)p->max_links);
   L.off_walls = off;
-  off += align_up((p->storage == LBM_FP64 ? sizeof(DevWall<double>) : sizeof(DevWall<float>)) *
+  off += align_up((arith64(p->storage) ? sizeof(DevWall<double>) : sizeof(DevWall<float>)) *
                   (size_t)p->max_links);
   L.off_special = off;
   off += align_up(sizeof(DevSpecial) * (size_t)p->max_special);
@@ -231,7 +239,7 @@ Layout layout(const lbm_params *p) {
   L.off_cols = off;
   off += align_up(sizeof(int32_t) * kMaxColumns);
   // AA side buffers (arithmetic type): per link f and h, 2 x 3 per boundary node
-  const size_t rsz = p->storage == LBM_FP64 ? 8 : 4;
+  const size_t rsz = arith64(p->storage) ? 8 : 4;
   const bool aa = p->stream == LBM_STREAM_AA;
   L.off_side_f = off;
   off += aa ? align_up(rsz * (size_t)p->max_links) : 0;
@@ -583,7 +591,8 @@ static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   a.row_blocks = 2 * ((ctx->p.nx + 255) / 256);
   // the swapped in-place phase of a lattice without geometry whose x-rows
   // are whole blocks realigns its x-pushes through LDS (k_bulk XR)
-  a.xr = !ctx->geom && ctx->p.storage != LBM_FP64 && ctx->p.nx % 256 == 0;
+  a.xr = !ctx->geom && !arith64(ctx->p.storage) && ctx->p.nx % 256 == 0;
+  a.sr_seed = sr_seed(ctx->t);
   // FP16 pairs address a byte offset of up to 4 Q (padded nodes) per slot base
   a.pair64 = (double)4 * ctx->Q * (double)plane_nodes(ctx->n, ctx->Q) >= 4294967296.0;
   for (int k = 0; k < 27; k++) {
@@ -833,7 +842,7 @@ lbm_status lbm_set_geometry(lbm_ctx *ctx, const uint16_t *flags, const double *q
     if (nl) {
       HIP_TRY(ctx, hipMemcpyAsync(ctx->ws + ctx->L.off_links, G.links.data(), sizeof(DevLink) * nl,
                                   hipMemcpyHostToDevice, ctx->stream), "copy links");
-      if (ctx->p.storage == LBM_FP64)
+      if (arith64(ctx->p.storage))
         wall_records<double>(G.links, dg, &walls);
       else
         wall_records<float>(G.links, dg, &walls);
@@ -992,6 +1001,7 @@ lbm_status lbm_set_populations(lbm_ctx *ctx, int32_t lattice, const double *src_
   const double ref = dev ? (lattice == 0 ? ctx->p.rho_ref : ctx->p.H_ref) : 0.0;
   KArgs a = make_args(ctx, ctx->cur);
   a.cls = nullptr;
+  a.sr_seed = sr_seed(t);
   HIP_TRY(ctx, launch_convert(ctx->Q, ctx->p.storage, ctx->lay(), true, a, src_dev, ctx->pop(lattice, ctx->cur), ref,
                               ctx->stream), "convert kernel launch");
   ctx->t = t;
@@ -1127,8 +1137,9 @@ lbm_status lbm_nusselt(lbm_ctx *ctx, int32_t group, int32_t x_in, int32_t x_out,
 }
 
 static lbm_status need_adjoint(lbm_ctx *ctx) {
-  if (ctx->p.with_ns || (ctx->p.cumulant & 1)) {
-    set_err(&ctx->err, "the adjoint is built for advection-only contexts with the central-moment collision");
+  if (ctx->p.with_ns || (ctx->p.cumulant & 1) || ctx->p.storage == LBM_FP32_SR) {
+    set_err(&ctx->err, "the adjoint is built for advection-only contexts with the central-moment collision "
+                       "(storage other than LBM_FP32_SR)");
     return LBM_EUNSUPPORTED;
   }
   if (ctx->p.u_mode == 1 && !ctx->uvel) {

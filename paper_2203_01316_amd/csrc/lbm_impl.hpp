@@ -66,6 +66,35 @@ struct StT<ST_FP16_DEV> {
   using R = float;
   static constexpr bool DEV = true;
 };
+template <>
+struct StT<ST_FP32_SR> {
+  using S = float;
+  using R = double;
+  static constexpr bool DEV = false;
+};
+
+// Stochastic rounding of the FP32_SR storage.  The draw is the 32-bit hash
+// "lowbias32" (C. Wellons' integer hash prospector, public domain) of the
+// storage location and the step counter.  Adding 29 of its bits to the 29
+// mantissa bits of a double that FP32 does not hold, then clearing them,
+// rounds the magnitude up with probability equal to the dropped fraction of
+// an FP32 ulp and down otherwise (both signs alike); the result is then an
+// exact FP32 value.
+__device__ __forceinline__ uint32_t sr_hash(uint32_t slot, uint32_t node, uint32_t seed) {
+  uint32_t x = node * 0x9E3779B9u ^ (slot + 1u) * 0x85EBCA6Bu ^ seed;
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+__device__ __forceinline__ float sr_round(double v, uint32_t r) {
+  unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+  b += static_cast<unsigned long long>(r >> 3);
+  b &= ~((1ull << 29) - 1ull);
+  return static_cast<float>(__longlong_as_double(static_cast<long long>(b)));
+}
 
 // Population storage.  FP64 and FP32 elements: tiles of
 // T = pop_tile_bytes(Q) / sizeof(S) consecutive nodes; a tile holds the Q
@@ -187,14 +216,19 @@ __device__ __forceinline__ typename StT<ST>::R ldp(const void *base, int slot, i
   return v;
 }
 
+// sr: the step's draw seed (FP32_SR storage only).
 template <int Q, int ST, int NL = 0>
 __device__ __forceinline__ void stp(void *base, int slot, int64_t ps, int64_t m, typename StT<ST>::R v,
-                                    typename StT<ST>::R ref) {
+                                    typename StT<ST>::R ref, uint32_t sr = 0) {
   using T = StT<ST>;
   if constexpr (T::DEV) v -= weight<Q, typename T::R>(slot) * ref;
   const global_ptr<typename T::S> p =
       uniform_base(static_cast<typename T::S *>(base) + slot_offset<Q, typename T::S, NL>(slot, ps));
-  StoreT<typename T::S>::st(elem_at<typename T::S, NL>(p, node_offset<Q, typename T::S, NL>(ps, m)), v);
+  if constexpr (ST == ST_FP32_SR)
+    StoreT<float>::st(elem_at<float, NL>(p, node_offset<Q, float, NL>(ps, m)),
+                      sr_round(v, sr_hash((uint32_t)slot, (uint32_t)m, sr)));
+  else
+    StoreT<typename T::S>::st(elem_at<typename T::S, NL>(p, node_offset<Q, typename T::S, NL>(ps, m)), v);
 }
 
 // FP16 pairs: both lattices of slot `slot` of node m with one 4-byte access
@@ -628,7 +662,7 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
         }
         if constexpr (PR) continue;
         store_addr<Q, LAY>(a, c, m, i, sl, nd);
-        stp<Q, ST, NS ? 2 : 1>(a.fdst, sl, a.ps, nd, f[i], R(a.fref));
+        stp<Q, ST, NS ? 2 : 1>(a.fdst, sl, a.ps, nd, f[i], R(a.fref), a.sr_seed);
       }
     }
 #pragma unroll
@@ -654,7 +688,7 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
       }
       if constexpr (PR) continue;
       store_addr<Q, LAY>(a, c, m, i, sl, nd);
-      stp<Q, ST, NS ? 2 : 1>(a.hdst, sl, a.ps, nd, h[i], R(a.href));
+      stp<Q, ST, NS ? 2 : 1>(a.hdst, sl, a.ps, nd, h[i], R(a.href), a.sr_seed ^ 0x5bd1e995u);
     }
     if constexpr (PR) {
       if (a.pair64)
@@ -1136,7 +1170,7 @@ __global__ void __launch_bounds__(256) k_convert(const KArgs a, const void *from
     int64_t nd;
     post_addr<Q, LAY>(a, c, m, i, sl, nd);
     if constexpr (TO_STORAGE)
-      stp<Q, ST, NL>(to, sl, a.ps, nd, R(static_cast<const double *>(from)[i * a.n + m]), R(ref));
+      stp<Q, ST, NL>(to, sl, a.ps, nd, R(static_cast<const double *>(from)[i * a.n + m]), R(ref), a.sr_seed);
     else
       static_cast<double *>(to)[i * a.n + m] = solid ? 0.0 : double(ldp<Q, ST, NL>(from, sl, a.ps, nd, R(ref)));
   }
@@ -1403,7 +1437,7 @@ constexpr size_t step_lds() {
 template <int Q, int ST, bool NS, bool GEOM, int LAY>
 static hipError_t pass_t(int mode, int cu, const KArgs &a, hipStream_t s) {
   const unsigned g = blocks_for(a.n, 256);
-  if constexpr (!GEOM && LAY == LAY_AA_S && ST != ST_FP64) {
+  if constexpr (!GEOM && LAY == LAY_AA_S && sizeof(typename StT<ST>::R) == 4) {
     if (mode == MODE_STEP && a.xr) {
       if (a.nx % 256 != 0) return hipErrorInvalidValue;
       constexpr size_t lx = xr_lds_bytes<Q, float>();

@@ -23,6 +23,8 @@ LBM_DECLARE(q27_fp64)
 LBM_DECLARE(q27_fp32)
 LBM_DECLARE(q27_fp32dev)
 LBM_DECLARE(q27_fp16dev)
+LBM_DECLARE(q9_fp32sr)
+LBM_DECLARE(q27_fp32sr)
 
 // (lattice, storage) -> the launcher of that translation unit
 #define LBM_SELECT(Q, ST, F, ...)                                              \
@@ -33,6 +35,7 @@ LBM_DECLARE(q27_fp16dev)
         case ST_FP32: return q9_fp32_##F(__VA_ARGS__);                         \
         case ST_FP32_DEV: return q9_fp32dev_##F(__VA_ARGS__);                  \
         case ST_FP16_DEV: return q9_fp16dev_##F(__VA_ARGS__);                  \
+        case ST_FP32_SR: return q9_fp32sr_##F(__VA_ARGS__);                    \
       }                                                                        \
     } else if (Q == 27) {                                                      \
       switch (ST) {                                                            \
@@ -40,6 +43,7 @@ LBM_DECLARE(q27_fp16dev)
         case ST_FP32: return q27_fp32_##F(__VA_ARGS__);                        \
         case ST_FP32_DEV: return q27_fp32dev_##F(__VA_ARGS__);                 \
         case ST_FP16_DEV: return q27_fp16dev_##F(__VA_ARGS__);                 \
+        case ST_FP32_SR: return q27_fp32sr_##F(__VA_ARGS__);                   \
       }                                                                        \
     }                                                                          \
     return hipErrorInvalidValue;                                               \

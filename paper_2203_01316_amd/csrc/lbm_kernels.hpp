@@ -108,6 +108,7 @@ struct KArgs {
   int32_t xr;              // swapped in-place phase without geometry: the x-pushes
                            // go through LDS (needs nx % 256 == 0)
   int32_t pair64;          // FP16 pairs: 64-bit lane offsets (4 Q n >= 2^32)
+  uint32_t sr_seed;        // FP32_SR: step counter hashed into the rounding draws
   double sf[27];           // rates of f, chimera order
   double sh[27];           // rates of h, chimera order
   float sf32[27];          // the same rates rounded for FP32 arithmetic
@@ -139,7 +140,7 @@ struct InitArgs {
 };
 
 // storage codes (lbm_storage)
-enum : int { ST_FP64 = 0, ST_FP32 = 1, ST_FP32_DEV = 2, ST_FP16_DEV = 3 };
+enum : int { ST_FP64 = 0, ST_FP32 = 1, ST_FP32_DEV = 2, ST_FP16_DEV = 3, ST_FP32_SR = 4 };
 
 // Launchers; return hipSuccess or the launch error.  lay: LAY_*.  cu: the
 // collision of each lattice in MODE_STEP (bit 0 h, bit 1 f: cumulants, else

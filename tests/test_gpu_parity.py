@@ -57,7 +57,8 @@ def test_ragged_sizes_fp64(L, oracle):
         assert rel_l2(gpu_pre(g), o.pre()[1]) < TOL64, dims
 
 
-@pytest.mark.parametrize("storage,tol", [("fp32", TOL32), ("fp32_dev", TOL32), ("fp16_dev", 2e-4)])
+@pytest.mark.parametrize("storage,tol", [("fp32", TOL32), ("fp32_dev", TOL32), ("fp16_dev", 2e-4),
+                                         ("fp32_sr", TOL32)])
 @pytest.mark.parametrize("stream", ["ab", "aa"])
 def test_ragged_sizes_coupled(L, oracle, storage, tol, stream):
     """Coupled f + h on lattices smaller than one population tile, with odd
@@ -103,7 +104,7 @@ def test_channel_links_bit_exact(L, oracle):
     assert len(o.links()) > 6000
 
 
-@pytest.mark.parametrize("storage,tol", [("fp64", TOL64), ("fp32", TOL32)])
+@pytest.mark.parametrize("storage,tol", [("fp64", TOL64), ("fp32", TOL32), ("fp32_sr", TOL32)])
 def test_channel_small(L, oracle, storage, tol):
     g, o = _channel(L, oracle, 160, 48, 40, 24, 7.5, storage)
     g.step(600)
@@ -144,7 +145,7 @@ def _cylinder(L, oracle, nx, ny, r, storage, nu=0.04, k=0.06, oracle_init=True, 
                 relax_h="1st" if cu else "trt", cu_f=cu, cu_h=cu)
 
 
-@pytest.mark.parametrize("storage,tol", [("fp64", TOL64), ("fp32", TOL32)])
+@pytest.mark.parametrize("storage,tol", [("fp64", TOL64), ("fp32", TOL32), ("fp32_sr", TOL32)])
 def test_cylinder_ns_ade_small(L, oracle, storage, tol):
     g, o = _cylinder(L, oracle, 192, 96, 9.5, storage)
     g.step(400)
@@ -646,3 +647,51 @@ def test_concentric_cylinders_convergence_on_gpu(L):
     print("orders", order)
     assert min(order["iabb"]) > 1.8, order
     assert max(order["abb"]) < 1.5 and max(order["eq"]) < 1.5, order
+
+
+# ---------------------------------------------------------------------------
+# FP32 storage with stochastic rounding
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("Q,stream", [(9, "ab"), (9, "aa"), (27, "ab")])
+def test_fp32_sr_rounding(L, Q, stream):
+    """FP32_SR writes each value as one of the two FP32 numbers around it
+    (exact FP32 values stay exact), rounding away from the nearer one with
+    probability equal to the distance in ulps: the mean rounding error is
+    within a few standard errors of zero and the share rounded up follows
+    the dropped fraction, while plain FP32 storage of the same values rounds
+    to nearest.  A repeated write at the same time is bit-identical; one at
+    another time draws again (two independent draws differ with probability
+    2 p (1 - p))."""
+    dims = (256, 256, 1) if Q == 9 else (64, 64, 16)
+    n = int(np.prod(dims))
+    rng = np.random.default_rng(81)
+    w = 1.0 / Q
+    v = w + rng.uniform(-1e-3, 1e-3, (Q, n))
+    v[0, :1000] = f32(v[0, :1000])          # already FP32
+    st = L.STREAM_AA if stream == "aa" else L.STREAM_AB
+    g = L.LBM(Q, *dims, storage="fp32_sr", k=0.02, stream=st)
+    g.set_populations("h", v, t=0)
+    a = g.populations("h", "post").cpu().numpy()
+    assert np.array_equal(a, f32(a))
+    down = np.float64(np.float32(v))
+    below = np.where(down > v, np.float64(np.nextafter(np.float32(v), np.float32(-1))), down)
+    above = np.float64(np.nextafter(below.astype(np.float32), np.float32(2)))
+    assert np.all((a == below) | (a == above) | (a == v))
+    assert np.array_equal(a[0, :1000], v[0, :1000])
+    ulp = above - below
+    err = (a - v) / ulp
+    frac = (v - below) / ulp
+    assert abs(err.mean()) < 5 * err.std() / np.sqrt(err.size)
+    # the share rounded up follows the dropped fraction
+    up = (a == above) & (v != below)
+    for lo_, hi_ in ((0.0, 0.25), (0.25, 0.5), (0.5, 0.75), (0.75, 1.0)):
+        sel = (frac > lo_) & (frac < hi_)
+        assert abs(up[sel].mean() - 0.5 * (lo_ + hi_)) < 0.01
+    g.set_populations("h", v, t=0)
+    assert np.array_equal(g.populations("h", "post").cpu().numpy(), a)
+    g.set_populations("h", v, t=1)
+    b = g.populations("h", "post").cpu().numpy()
+    assert abs(np.mean(a != b) - np.mean(2 * frac * (1 - frac))) < 0.01
+    r = L.LBM(Q, *dims, storage="fp32", k=0.02, stream=st)
+    r.set_populations("h", v, t=0)
+    assert np.array_equal(r.populations("h", "post").cpu().numpy(), f32(v))
