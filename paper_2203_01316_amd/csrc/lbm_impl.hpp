@@ -1421,7 +1421,10 @@ static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b -
 // D3Q27 steps and the full cumulant transform measured no gain or a loss.  The in-place D3Q27 FP16
 // central-moment step takes 630 us at 3 blocks per CU in its streamed phase
 // against 646 uncapped (641 at 2, 632 at 4; the swapped phase holds 4 blocks
-// per CU through its LDS exchange).  0 = no cap.
+// per CU through its LDS exchange).  FP32 storage with FP64 arithmetic
+// (stochastic rounding): the in-place D3Q27 step takes 1288 us at 2 blocks
+// per CU against 1330 uncapped; its two-array D3Q27 and its D2Q9 steps run
+// fastest uncapped.  0 = no cap.
 constexpr size_t lds_for_blocks(int blocks) { return (size_t)(160 * 1024) / (blocks + 1) + 1024; }
 
 template <int Q, int ST, int LAY, int CU>
@@ -1429,6 +1432,8 @@ constexpr size_t step_lds() {
   constexpr bool fp32 = (ST == ST_FP32 || ST == ST_FP32_DEV) && ((CU & 7) == 0 || (CU & 4));
   if constexpr (Q == 27 && fp32) return lds_for_blocks(2);
   if constexpr (Q == 27 && ST == ST_FP16_DEV && LAY == LAY_AA_N && (CU & 7) == 0) return lds_for_blocks(3);
+  if constexpr (Q == 27 && ST == ST_FP32_SR && LAY != LAY_AB && ((CU & 7) == 0 || (CU & 4)))
+    return lds_for_blocks(2);
   if constexpr (Q == 9 && fp32 && LAY == LAY_AB) return lds_for_blocks(3);
   if constexpr (Q == 9 && ST == ST_FP64 && LAY == LAY_AB && ((CU & 7) == 0 || (CU & 4))) return lds_for_blocks(2);
   return 0;
