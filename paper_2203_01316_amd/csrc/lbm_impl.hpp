@@ -73,15 +73,19 @@ struct StT<ST_FP32_SR> {
   static constexpr bool DEV = false;
 };
 
-// Stochastic rounding of the FP32_SR storage.  The draw is the 32-bit hash
-// "lowbias32" (C. Wellons' integer hash prospector, public domain) of the
-// storage location and the step counter.  Adding 29 of its bits to the 29
+// Stochastic rounding of the FP32_SR storage.  A node draws one 32-bit
+// value per step, the hash "lowbias32" (C. Wellons' integer hash prospector,
+// public domain) of the node and the step's seed; the k-th value it stores
+// in that step (f then h, direction order) takes the draw plus k times the
+// golden-ratio increment 2^32 / phi (a Weyl sequence), so each draw stays
+// uniform and each rounding unbiased.  Adding 29 bits of a draw to the 29
 // mantissa bits of a double that FP32 does not hold, then clearing them,
 // rounds the magnitude up with probability equal to the dropped fraction of
 // an FP32 ulp and down otherwise (both signs alike); the result is then an
 // exact FP32 value.
-__device__ __forceinline__ uint32_t sr_hash(uint32_t slot, uint32_t node, uint32_t seed) {
-  uint32_t x = node * 0x9E3779B9u ^ (slot + 1u) * 0x85EBCA6Bu ^ seed;
+constexpr uint32_t SR_WEYL = 0x9E3779B9u;
+__device__ __forceinline__ uint32_t sr_hash(uint32_t node, uint32_t seed) {
+  uint32_t x = node * SR_WEYL ^ seed;
   x ^= x >> 16;
   x *= 0x7feb352du;
   x ^= x >> 15;
@@ -216,7 +220,7 @@ __device__ __forceinline__ typename StT<ST>::R ldp(const void *base, int slot, i
   return v;
 }
 
-// sr: the step's draw seed (FP32_SR storage only).
+// sr: the value's rounding draw (FP32_SR storage only).
 template <int Q, int ST, int NL = 0>
 __device__ __forceinline__ void stp(void *base, int slot, int64_t ps, int64_t m, typename StT<ST>::R v,
                                     typename StT<ST>::R ref, uint32_t sr = 0) {
@@ -225,8 +229,7 @@ __device__ __forceinline__ void stp(void *base, int slot, int64_t ps, int64_t m,
   const global_ptr<typename T::S> p =
       uniform_base(static_cast<typename T::S *>(base) + slot_offset<Q, typename T::S, NL>(slot, ps));
   if constexpr (ST == ST_FP32_SR)
-    StoreT<float>::st(elem_at<float, NL>(p, node_offset<Q, float, NL>(ps, m)),
-                      sr_round(v, sr_hash((uint32_t)slot, (uint32_t)m, sr)));
+    StoreT<float>::st(elem_at<float, NL>(p, node_offset<Q, float, NL>(ps, m)), sr_round(v, sr));
   else
     StoreT<typename T::S>::st(elem_at<typename T::S, NL>(p, node_offset<Q, typename T::S, NL>(ps, m)), v);
 }
@@ -636,6 +639,7 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
   else if constexpr (!NS)
     prescribed_u<Q, R>(a, m, ux, uy, uz);
   const R src = a.src ? static_cast<const R *>(a.src)[m] : R(0);
+  const uint32_t sr = ST == ST_FP32_SR ? sr_hash((uint32_t)m, a.sr_seed) : 0u;
   if constexpr (MODE == MODE_STEP) {
     R g[Q];
     if constexpr (NS) {
@@ -662,7 +666,7 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
         }
         if constexpr (PR) continue;
         store_addr<Q, LAY>(a, c, m, i, sl, nd);
-        stp<Q, ST, NS ? 2 : 1>(a.fdst, sl, a.ps, nd, f[i], R(a.fref), a.sr_seed);
+        stp<Q, ST, NS ? 2 : 1>(a.fdst, sl, a.ps, nd, f[i], R(a.fref), sr + (uint32_t)i * SR_WEYL);
       }
     }
 #pragma unroll
@@ -688,7 +692,7 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
       }
       if constexpr (PR) continue;
       store_addr<Q, LAY>(a, c, m, i, sl, nd);
-      stp<Q, ST, NS ? 2 : 1>(a.hdst, sl, a.ps, nd, h[i], R(a.href), a.sr_seed ^ 0x5bd1e995u);
+      stp<Q, ST, NS ? 2 : 1>(a.hdst, sl, a.ps, nd, h[i], R(a.href), sr + (uint32_t)(Q + i) * SR_WEYL);
     }
     if constexpr (PR) {
       if (a.pair64)
@@ -1146,11 +1150,14 @@ __global__ void __launch_bounds__(256) k_init(const InitArgs a) {
     }
     if (Lat<Q>::D == 2) uz = 0.0;
     const int slot = LAY == LAY_AB ? i : Lat<Q>::opp(i);
+    const uint32_t sr = ST == ST_FP32_SR ? sr_hash((uint32_t)m, 0u) : 0u;
     if constexpr (NS) {
       const double rho = a.rho ? a.rho[s] : 1.0;
-      stp<Q, ST, NS ? 2 : 1>(a.fdst, slot, a.ps, m, R(geq_dir<Q, double>(i, rho, ux, uy, uz)), R(a.fref));
+      stp<Q, ST, NS ? 2 : 1>(a.fdst, slot, a.ps, m, R(geq_dir<Q, double>(i, rho, ux, uy, uz)), R(a.fref),
+                             sr + (uint32_t)i * SR_WEYL);
     }
-    stp<Q, ST, NS ? 2 : 1>(a.hdst, slot, a.ps, m, R(geq_dir<Q, double>(i, a.H[s], ux, uy, uz)), R(a.href));
+    stp<Q, ST, NS ? 2 : 1>(a.hdst, slot, a.ps, m, R(geq_dir<Q, double>(i, a.H[s], ux, uy, uz)), R(a.href),
+                           sr + (uint32_t)(Q + i) * SR_WEYL);
   }
 }
 
@@ -1164,13 +1171,15 @@ __global__ void __launch_bounds__(256) k_convert(const KArgs a, const void *from
   if (m >= a.n) return;
   const Node c = coords<Q>(a, m);
   const bool solid = a.cls && a.cls[m] == CLS_SOLID;
+  const uint32_t sr = ST == ST_FP32_SR ? sr_hash((uint32_t)m, a.sr_seed) : 0u;
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     int sl;
     int64_t nd;
     post_addr<Q, LAY>(a, c, m, i, sl, nd);
     if constexpr (TO_STORAGE)
-      stp<Q, ST, NL>(to, sl, a.ps, nd, R(static_cast<const double *>(from)[i * a.n + m]), R(ref), a.sr_seed);
+      stp<Q, ST, NL>(to, sl, a.ps, nd, R(static_cast<const double *>(from)[i * a.n + m]), R(ref),
+                     sr + (uint32_t)i * SR_WEYL);
     else
       static_cast<double *>(to)[i * a.n + m] = solid ? 0.0 : double(ldp<Q, ST, NL>(from, sl, a.ps, nd, R(ref)));
   }
