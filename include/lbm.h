@@ -70,11 +70,11 @@ typedef enum { LBM_D2Q9 = 9, LBM_D3Q27 = 27 } lbm_lattice;
  * g_ref from the rest equilibrium of the reference values rho_ref / H_ref.
  * LBM_FP32_SR stores FP32 values rounded stochastically from the FP64 result:
  * up or down to the two nearest FP32 values with probabilities set by the
- * distance to each, drawn from a hash of the storage location and the step
- * (deterministic for a given run).  A steady state then does not accumulate
- * the bias that rounding to nearest repeats at every node and step; the
- * in-place and two-array layouts round at different locations and agree to
- * rounding, not bit for bit.  No adjoint. */
+ * distance to each, drawn from a hash of the updating node and the step and
+ * the value's lattice and direction (deterministic for a given run, and the
+ * same in the in-place and two-array layouts, which agree bit for bit).  A
+ * steady state then does not accumulate the bias that rounding to nearest
+ * repeats at every node and step.  No adjoint. */
 typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP32_DEV = 2, LBM_FP16_DEV = 3, LBM_FP32_SR = 4 } lbm_storage;
 
 /* Streaming layout: two arrays (AB) or one array updated in place (AA). */

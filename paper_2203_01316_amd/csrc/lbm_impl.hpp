@@ -286,10 +286,13 @@ __device__ __forceinline__ void stp_pair(void *fbase, int slot, int64_t m, float
 
 // Value a store followed by a load of population i would return.
 template <int Q, int ST>
-__device__ __forceinline__ typename StT<ST>::R roundtrip(int i, typename StT<ST>::R v, typename StT<ST>::R ref) {
+__device__ __forceinline__ typename StT<ST>::R roundtrip(int i, typename StT<ST>::R v, typename StT<ST>::R ref,
+                                                         uint32_t sr = 0) {
   using T = StT<ST>;
   using R = typename T::R;
-  if constexpr (!T::DEV) {
+  if constexpr (ST == ST_FP32_SR) {
+    return R(sr_round(v, sr));
+  } else if constexpr (!T::DEV) {
     return v;
   } else {
     const R d = v - weight<Q, R>(i) * ref;
@@ -994,15 +997,17 @@ __device__ __forceinline__ void pull_links(const KArgs &a, int64_t m, int32_t lb
 }
 
 // AA side values of one boundary node after its update: g*_opp(i)(x_b) per
-// link and the velocity of the stored f, both as they read back from storage.
+// link and the velocity of the stored f, both as they read back from storage
+// (sr: the node's rounding draw of the step, FP32_SR storage).
 template <int Q, int ST, bool NS>
 __device__ __forceinline__ void save_side(const KArgs &a, int32_t lb, uint32_t mask, int64_t side_node,
-                                          const typename StT<ST>::R *fpost, const typename StT<ST>::R *hpost) {
+                                          const typename StT<ST>::R *fpost, const typename StT<ST>::R *hpost,
+                                          uint32_t sr = 0) {
   using R = typename StT<ST>::R;
   if constexpr (NS) {
     R fr[Q], rho, ux, uy, uz;
 #pragma unroll
-    for (int i = 0; i < Q; i++) fr[i] = roundtrip<Q, ST>(i, fpost[i], R(a.fref));
+    for (int i = 0; i < Q; i++) fr[i] = roundtrip<Q, ST>(i, fpost[i], R(a.fref), sr + (uint32_t)i * SR_WEYL);
     if (mask) {
       R *su = static_cast<R *>(a.side_u) + 3 * side_node;
       velocity_dir<Q, R>(fr, rho, ux, uy, uz);
@@ -1022,7 +1027,7 @@ __device__ __forceinline__ void save_side(const KArgs &a, int32_t lb, uint32_t m
     if (!((mask >> i) & 1u)) continue;
     const int32_t l = lb + __popc(mask & ((1u << i) - 1u));
     const int o = Lat<Q>::opp(i);
-    static_cast<R *>(a.side_h)[l] = roundtrip<Q, ST>(o, hpost[o], R(a.href));
+    static_cast<R *>(a.side_h)[l] = roundtrip<Q, ST>(o, hpost[o], R(a.href), sr + (uint32_t)(Q + o) * SR_WEYL);
   }
 }
 
@@ -1055,12 +1060,15 @@ __device__ __forceinline__ void special_node(const KArgs &a, int64_t t) {
       }
       if constexpr (AA) {
         finish_node<Q, ST, NS, MODE, LAY, CU>(a, coords<Q>(a, up), up, fu, hu);
-        if constexpr (MODE == MODE_STEP) save_side<Q, ST, NS>(a, sp.ub, sp.umask, 2 * t + 1, fu, hu);
+        if constexpr (MODE == MODE_STEP)
+          save_side<Q, ST, NS>(a, sp.ub, sp.umask, 2 * t + 1, fu, hu,
+                               ST == ST_FP32_SR ? sr_hash((uint32_t)up, a.sr_seed) : 0u);
       }
     }
   }
   finish_node<Q, ST, NS, MODE, LAY, CU>(a, c, m, f, h);
-  if constexpr (AA && MODE == MODE_STEP) save_side<Q, ST, NS>(a, sp.lb, sp.mask, 2 * t, f, h);
+  if constexpr (AA && MODE == MODE_STEP)
+    save_side<Q, ST, NS>(a, sp.lb, sp.mask, 2 * t, f, h, ST == ST_FP32_SR ? sr_hash((uint32_t)m, a.sr_seed) : 0u);
 }
 
 template <int Q, int ST, bool NS, int MODE, int LAY, int CU = 0>

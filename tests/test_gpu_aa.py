@@ -1,7 +1,10 @@
 """In-place (AA) streaming against two-array (AB) streaming: the same
 arithmetic on every node, so the canonical states, the stored post-collision
 states, the macroscopic fields and the reductions agree bit for bit after odd
-and even step counts, with walls, interpolated walls, EQ nodes and outlets."""
+and even step counts, with walls, interpolated walls, EQ nodes and outlets.
+With stochastic rounding (FP32-SR) the draws follow the updating node and
+the value's direction, so both layouts make the same draws and agree bit for
+bit too."""
 import numpy as np
 import pytest
 
@@ -43,7 +46,7 @@ def _same(L, ab, aa, lattices, exact=True, cols=(), group=0):
         assert np.array_equal(Ha.cpu().numpy(), Hb.cpu().numpy())
 
 
-@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp32_sr"])
 def test_aa_periodic_hill(L, storage):
     H0 = W.gaussian_hill(64, 8.0, 0.5, None, (0.05, 0.02), 0.01, 0.0)
 
@@ -59,7 +62,7 @@ def test_aa_periodic_hill(L, storage):
         _same(L, ab, aa, ("h",))
 
 
-@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp32_sr"])
 def test_aa_channel(L, storage):
     flags, q, groups, u = W.channel(160, 48, 40, 24, 7.5, 0.05)
     uu = f32(u) if storage == "fp32" else u
@@ -77,7 +80,7 @@ def test_aa_channel(L, storage):
         _same(L, ab, aa, ("h",), cols=(10, 80, 159), group=2)
 
 
-@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp32_sr"])
 def test_aa_coupled_cylinder(L, storage):
     flags, q, groups, u, rho0, H0 = W.heated_cylinder(192, 96, 9.5, u_in=0.04, amp=1e-3, seed=0)
     uu = f32(u) if storage == "fp32" else u
@@ -96,7 +99,7 @@ def test_aa_coupled_cylinder(L, storage):
         _same(L, ab, aa, ("f", "h"), cols=(5, 150), group=1)
 
 
-@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp32_sr"])
 def test_aa_boundary_mix(L, storage):
     """Listed outlets (the thread also updates the upstream node) next to
     bulk-handled ones (the upstream populations come from the previous lane)."""
@@ -117,7 +120,7 @@ def test_aa_boundary_mix(L, storage):
         _same(L, ab, aa, ("f", "h"), cols=(2, 31, 32), group=2)
 
 
-@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+@pytest.mark.parametrize("storage", ["fp32", "fp64", "fp32_sr"])
 def test_aa_d3q27_sphere(L, storage):
     nx, ny, nz = 20, 14, 12
     flags, q, groups = W.sphere_box(nx, ny, nz, (9.3, 6.6, 5.8), 3.4, inlet=True)
@@ -142,7 +145,7 @@ def test_aa_d3q27_sphere(L, storage):
 
 
 @pytest.mark.parametrize("cu", [False, True])
-@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+@pytest.mark.parametrize("storage", ["fp32", "fp64", "fp32_sr"])
 def test_aa_d3q27_several_tiles(L, storage, cu):
     """Several population tiles with a ragged last one (19,200 nodes), sphere,
     inlet and outlet, central-moment or cumulant kernels (the in-place steps

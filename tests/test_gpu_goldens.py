@@ -105,11 +105,13 @@ def test_c2_channel_20000_steps(L, stream, storage, tol, tol_node):
 # ---------------------------------------------------------------------------
 # Config 3 parity window: 2048^2 coupled heated cylinder, 200 steps
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("storage,tol,tol_node", [("fp32", TOL32, 1e-4), ("fp16_dev", 2e-4, 2e-3)])
+@pytest.mark.parametrize("storage,tol,tol_node", [("fp32", TOL32, 1e-4), ("fp16_dev", 2e-4, 2e-3),
+                                                  ("fp32_sr", TOL32, 1e-4)])
 @pytest.mark.parametrize("stream", ["ab", "aa"])
 def test_c3_cylinder_200_steps(L, storage, tol, tol_node, stream):
-    """FP32 within 1e-5; FP16 deviation storage (rho_ref = 1, H_ref = 10)
-    within 2e-4 over the stored nodes and 2e-3 at any one of them."""
+    """FP32 (plain, or FP64 arithmetic with stochastic rounding) within 1e-5;
+    FP16 deviation storage (rho_ref = 1, H_ref = 10) within 2e-4 over the
+    stored nodes and 2e-3 at any one of them."""
     gd = _gold("c3_cylinder_2048_t200")
     nx = ny = 2048
     nu = 0.04 * 128 / 100.0
@@ -151,11 +153,12 @@ def _tgv(L, n1, storage, stream, cu):
 
 @pytest.mark.parametrize("name,n1,cu", [("c4_tgv_64_t200", 64, False), ("c4_tgv_64_cu_t200", 64, True),
                                         ("c4_tgv_256_t10", 256, False)])
-@pytest.mark.parametrize("storage,tol", [("fp32", TOL32), ("fp16_dev", 2e-4)])
+@pytest.mark.parametrize("storage,tol", [("fp32", TOL32), ("fp16_dev", 2e-4), ("fp32_sr", TOL32)])
 @pytest.mark.parametrize("stream", ["ab", "aa"])
 def test_c4_taylor_green(L, name, n1, cu, storage, tol, stream):
-    """FP32 within 1e-5 relative L2 on 2048 sampled nodes of both lattices;
-    FP16 deviation storage (references 1) within 2e-4; mass and energy sums."""
+    """FP32 (plain, or FP64 arithmetic with stochastic rounding) within 1e-5
+    relative L2 on 2048 sampled nodes of both lattices; FP16 deviation
+    storage (references 1) within 2e-4; mass and energy sums."""
     gd = _gold(name)
     g = _tgv(L, n1, storage, stream, cu)
     g.step(int(gd["t"]))
