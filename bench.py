@@ -149,7 +149,7 @@ def leg_cylinder(torch, L, W, np, storage, stream, nx, ny, steps, cu_f=False, cu
     g.set_velocity(uf)
     g.init(H0, u=uf.astype(np.float64), rho=rho0)
     sec = time_steps(torch, g, steps, steps)
-    bpn = 2 * 2 * 9 * (8 if storage == "fp64" else 2 if storage == "fp16_dev" else 4)
+    bpn = 2 * 2 * 9 * (8 if storage == "fp64" else 2 if storage.startswith("fp16") else 4)
     mlups = nx * ny / sec / 1e6
     del g
     torch.cuda.empty_cache()
@@ -169,7 +169,7 @@ def leg_tgv(torch, L, W, storage, n1, steps, cu=False, stream="ab"):
     del rho, u, H
     sec = time_steps(torch, g, steps, steps)
     red = g.reduce()
-    bpn = 2 * 2 * 27 * (2 if storage == "fp16_dev" else 4)
+    bpn = 2 * 2 * 27 * (2 if storage.startswith("fp16") else 4)
     mlups = n1 ** 3 / sec / 1e6
     out = {"workload": f"d3q27_ns_ade_taylor_green_{n1}^3", "storage": storage, "stream": stream.upper(),
            "collision": "f cumulant, h Cumulants-1st" if cu else "f CM-NS, h CM-TRT",
@@ -444,7 +444,10 @@ def main():
                        # FP32 storage, FP64 arithmetic, stochastic rounding on store
                        leg_cylinder(torch, L, W, np, "fp32_sr", "ab", nx, ny, max(10, int(1000 * sc))),
                        leg_cylinder(torch, L, W, np, "fp32_sr", "aa", nx, ny, max(10, int(1000 * sc))),
-                       leg_tgv(torch, L, W, "fp32_sr", 256, max(5, int(100 * sc)))]
+                       leg_tgv(torch, L, W, "fp32_sr", 256, max(5, int(100 * sc))),
+                       # FP16 deviations rounded stochastically
+                       leg_cylinder(torch, L, W, np, "fp16_sr", "ab", nx, ny, max(10, int(1000 * sc))),
+                       leg_tgv(torch, L, W, "fp16_sr", 256, max(5, int(100 * sc)))]
         out["adjoint"] = leg_adjoint(torch, L, np, steps=max(90, int(2000 * sc)))
         # headline: the checkpointed gradient with its forward replay (sqrt(T)
         # checkpoints); without the replay alongside

@@ -66,7 +66,7 @@ typedef enum {
 typedef enum { LBM_D2Q9 = 9, LBM_D3Q27 = 27 } lbm_lattice;
 
 /* Storage type of the populations; arithmetic is FP64 for LBM_FP64 and
- * LBM_FP32_SR and FP32 otherwise.  The *_DEV types store deviations g_i - w_i
+ * LBM_FP32_SR and FP32 otherwise.  The *_DEV types and LBM_FP16_SR store deviations g_i - w_i
  * g_ref from the rest equilibrium of the reference values rho_ref / H_ref.
  * LBM_FP32_SR stores FP32 values rounded stochastically from the FP64 result:
  * up or down to the two nearest FP32 values with probabilities set by the
@@ -74,8 +74,18 @@ typedef enum { LBM_D2Q9 = 9, LBM_D3Q27 = 27 } lbm_lattice;
  * the value's lattice and direction (deterministic for a given run, and the
  * same in the in-place and two-array layouts, which agree bit for bit).  A
  * steady state then does not accumulate the bias that rounding to nearest
- * repeats at every node and step.  No adjoint. */
-typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP32_DEV = 2, LBM_FP16_DEV = 3, LBM_FP32_SR = 4 } lbm_storage;
+ * repeats at every node and step.  No adjoint.
+ * LBM_FP16_SR is LBM_FP16_DEV (FP32 arithmetic, FP16 deviations) with the
+ * deviations rounded stochastically the same way (FP16 subnormals: to the
+ * multiples of 2^-24 around them).  No adjoint. */
+typedef enum {
+  LBM_FP64 = 0,
+  LBM_FP32 = 1,
+  LBM_FP32_DEV = 2,
+  LBM_FP16_DEV = 3,
+  LBM_FP32_SR = 4,
+  LBM_FP16_SR = 5
+} lbm_storage;
 
 /* Streaming layout: two arrays (AB) or one array updated in place (AA). */
 typedef enum { LBM_STREAM_AB = 0, LBM_STREAM_AA = 1 } lbm_stream_mode;
@@ -145,7 +155,7 @@ typedef struct {
                         * to rounding; other rates run the full one. */
   double nu;        /* kinematic viscosity (lattice units), f lattice */
   double k;         /* conductivity / diffusivity (lattice units), h lattice */
-  double rho_ref;   /* deviation reference of f (the *_DEV storages) */
+  double rho_ref;   /* deviation reference of f (the *_DEV storages, LBM_FP16_SR) */
   double H_ref;     /* deviation reference of h */
   double u0[3];     /* uniform advection velocity (u_mode 0) */
   double s_custom_f[27]; /* per-moment rates, LBM_CM_CUSTOM */

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "liblbm.so")
-SOURCES = [f"lbm_q{q}_{st}.hip" for q in (9, 27) for st in ("fp64", "fp32", "fp32dev", "fp16dev", "fp32sr")] + [
+SOURCES = [f"lbm_q{q}_{st}.hip" for q in (9, 27) for st in ("fp64", "fp32", "fp32dev", "fp16dev", "fp32sr", "fp16sr")] + [
     "lbm_kernels.hip", "lbm_host.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -81,7 +81,8 @@ size_t storage_size(int st) {
     case LBM_FP32:
     case LBM_FP32_DEV:
     case LBM_FP32_SR: return 4;
-    case LBM_FP16_DEV: return 2;
+    case LBM_FP16_DEV:
+    case LBM_FP16_SR: return 2;
     default: return 0;
   }
 }
@@ -92,6 +93,11 @@ bool arith64(int st) { return st == LBM_FP64 || st == LBM_FP32_SR; }
 // Seed of the FP32_SR rounding draws of the writes made at time t: a new
 // draw per step (Fibonacci hashing of t).
 static uint32_t sr_seed(int64_t t) { return (uint32_t)((uint64_t)t * 0x9E3779B97F4A7C15ull >> 32); }
+
+// FP16 deviation storage (either rounding); storage of deviations from the
+// reference values (FP32 or FP16).
+static bool half16(int st) { return st == LBM_FP16_DEV || st == LBM_FP16_SR; }
+static bool deviations(int st) { return st == LBM_FP32_DEV || half16(st); }
 
 bool set_err(std::string *dst, const char *fmt, ...) {
   char buf[512];
@@ -199,7 +205,7 @@ Layout layout(const lbm_params *p) {
   // (f, h) pairs (FP16 with both lattices: h starts one element after f), or
   // Q planes of plane_nodes() elements (FP16, h only).
   const size_t es = storage_size(p->storage);
-  const bool fp16 = p->storage == LBM_FP16_DEV;
+  const bool fp16 = half16(p->storage);
   const bool planes = fp16 && !p->with_ns;
   const int nlat = p->with_ns ? 2 : 1;
   L.pop_bytes = align_up((size_t)Q * plane_nodes(n, Q) * es);
@@ -581,7 +587,7 @@ static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   // planes one slab per XCD (dispatch order in the streamed AA phase); D3Q27
   // tiles dispatch order (the orders measured within 1% of each other);
   // D3Q27 FP16 planes chunks of two x-rows per XCD.  FP16 pairs are tiles.
-  const bool planes = ctx->p.storage == LBM_FP16_DEV && !ctx->p.with_ns;
+  const bool planes = half16(ctx->p.storage) && !ctx->p.with_ns;
   if (ctx->Q == 27)
     a.tilemap = planes ? 1 : 2;
   else if (!planes)
@@ -606,7 +612,7 @@ static KArgs make_args(lbm_ctx *ctx, int src_copy) {
   a.dbulk_f = sb > 0.0 ? sb - ctx->sfc[2] : 0.0;
   a.dbulk_f32 = sb > 0.0 ? (float)sb - (float)ctx->sfc[2] : 0.0f;
   for (int d = 0; d < 3; d++) a.u0[d] = ctx->p.u0[d];
-  const bool dev = ctx->p.storage == LBM_FP32_DEV || ctx->p.storage == LBM_FP16_DEV;
+  const bool dev = deviations(ctx->p.storage);
   a.fref = dev ? ctx->p.rho_ref : 0.0;
   a.href = dev ? ctx->p.H_ref : 0.0;
   return a;
@@ -917,7 +923,7 @@ lbm_status lbm_init_equilibrium(lbm_ctx *ctx, const double *rho_dev, const doubl
   a.ny = ctx->p.ny;
   a.nz = ctx->p.nz;
   for (int d = 0; d < 3; d++) a.u0[d] = ctx->p.u0[d];
-  const bool dev = ctx->p.storage == LBM_FP32_DEV || ctx->p.storage == LBM_FP16_DEV;
+  const bool dev = deviations(ctx->p.storage);
   a.fref = dev ? ctx->p.rho_ref : 0.0;
   a.href = dev ? ctx->p.H_ref : 0.0;
   HIP_TRY(ctx, launch_init(ctx->Q, ctx->p.storage, ctx->p.with_ns, ctx->lay(), a, ctx->stream),
@@ -976,7 +982,7 @@ lbm_status lbm_get_populations(lbm_ctx *ctx, int32_t lattice, int32_t which, dou
   }
   if (lbm_status st = need_ready(ctx)) return st;
   if (lbm_status st = activate(ctx)) return st;
-  const bool dev = ctx->p.storage == LBM_FP32_DEV || ctx->p.storage == LBM_FP16_DEV;
+  const bool dev = deviations(ctx->p.storage);
   if (which == 1) {
     const double ref = dev ? (lattice == 0 ? ctx->p.rho_ref : ctx->p.H_ref) : 0.0;
     KArgs a = make_args(ctx, ctx->cur);
@@ -997,7 +1003,7 @@ lbm_status lbm_set_populations(lbm_ctx *ctx, int32_t lattice, const double *src_
     return LBM_EINVAL;
   }
   if (lbm_status st = activate(ctx)) return st;
-  const bool dev = ctx->p.storage == LBM_FP32_DEV || ctx->p.storage == LBM_FP16_DEV;
+  const bool dev = deviations(ctx->p.storage);
   const double ref = dev ? (lattice == 0 ? ctx->p.rho_ref : ctx->p.H_ref) : 0.0;
   KArgs a = make_args(ctx, ctx->cur);
   a.cls = nullptr;
@@ -1137,9 +1143,9 @@ lbm_status lbm_nusselt(lbm_ctx *ctx, int32_t group, int32_t x_in, int32_t x_out,
 }
 
 static lbm_status need_adjoint(lbm_ctx *ctx) {
-  if (ctx->p.with_ns || (ctx->p.cumulant & 1) || ctx->p.storage == LBM_FP32_SR) {
+  if (ctx->p.with_ns || (ctx->p.cumulant & 1) || ctx->p.storage == LBM_FP32_SR || ctx->p.storage == LBM_FP16_SR) {
     set_err(&ctx->err, "the adjoint is built for advection-only contexts with the central-moment collision "
-                       "(storage other than LBM_FP32_SR)");
+                       "(storage other than LBM_FP32_SR and LBM_FP16_SR)");
     return LBM_EUNSUPPORTED;
   }
   if (ctx->p.u_mode == 1 && !ctx->uvel) {

@@ -72,6 +72,16 @@ struct StT<ST_FP32_SR> {
   using R = double;
   static constexpr bool DEV = false;
 };
+template <>
+struct StT<ST_FP16_SR> {
+  using S = __half;
+  using R = float;
+  static constexpr bool DEV = true;
+};
+// FP16 deviation storage (either rounding), and the storages that round
+// stochastically.
+__host__ __device__ constexpr bool half_st(int st) { return st == ST_FP16_DEV || st == ST_FP16_SR; }
+__host__ __device__ constexpr bool sr_st(int st) { return st == ST_FP32_SR || st == ST_FP16_SR; }
 
 // Stochastic rounding of the FP32_SR storage.  A node draws one 32-bit
 // value per step, the hash "lowbias32" (C. Wellons' integer hash prospector,
@@ -98,6 +108,17 @@ __device__ __forceinline__ float sr_round(double v, uint32_t r) {
   b += static_cast<unsigned long long>(r >> 3);
   b &= ~((1ull << 29) - 1ull);
   return static_cast<float>(__longlong_as_double(static_cast<long long>(b)));
+}
+// FP16_SR: an FP32 deviation rounded stochastically to FP16, returned as the
+// FP32 value of that FP16 number (so the conversion that follows is exact).
+// In the normal FP16 range (|d| >= 2^-14) 13 bits of the draw go to the 13
+// mantissa bits that FP16 drops, as for FP32_SR; below it FP16 holds the
+// multiples of 2^-24, and d 2^24 plus a uniform fraction is rounded down.
+__device__ __forceinline__ float sr16_round(float d, uint32_t r) {
+  const uint32_t b = __float_as_uint(d);
+  if ((b & 0x7fffffffu) >= 0x38800000u) return __uint_as_float((b + (r >> 19)) & ~0x1fffu);
+  const float q = floorf(fabsf(d) * 0x1p24f + static_cast<float>(r >> 8) * 0x1p-24f);
+  return copysignf(q * 0x1p-24f, d);
 }
 
 // Population storage.  FP64 and FP32 elements: tiles of
@@ -230,6 +251,8 @@ __device__ __forceinline__ void stp(void *base, int slot, int64_t ps, int64_t m,
       uniform_base(static_cast<typename T::S *>(base) + slot_offset<Q, typename T::S, NL>(slot, ps));
   if constexpr (ST == ST_FP32_SR)
     StoreT<float>::st(elem_at<float, NL>(p, node_offset<Q, float, NL>(ps, m)), sr_round(v, sr));
+  else if constexpr (ST == ST_FP16_SR)
+    StoreT<__half>::st(elem_at<__half, NL>(p, node_offset<Q, __half, NL>(ps, m)), sr16_round(v, sr));
   else
     StoreT<typename T::S>::st(elem_at<typename T::S, NL>(p, node_offset<Q, typename T::S, NL>(ps, m)), v);
 }
@@ -275,12 +298,19 @@ __device__ __forceinline__ void ldp_pair(const void *fbase, int slot, int64_t m,
   h = (float)w.y + weight<Q, float>(slot) * href;
 }
 
-template <int Q, bool W64>
-__device__ __forceinline__ void stp_pair(void *fbase, int slot, int64_t m, float f, float h, float fref, float href) {
+// SR: FP16_SR storage, with the rounding draws rf and rh of the two values.
+template <int Q, bool W64, bool SR = false>
+__device__ __forceinline__ void stp_pair(void *fbase, int slot, int64_t m, float f, float h, float fref, float href,
+                                         uint32_t rf = 0, uint32_t rh = 0) {
   const global_ptr<char> p = uniform_base(const_cast<char *>(pair_slot_base<Q>(fbase, slot)));
   hpair w;
-  w.x = (_Float16)(f - weight<Q, float>(slot) * fref);
-  w.y = (_Float16)(h - weight<Q, float>(slot) * href);
+  if constexpr (SR) {
+    w.x = (_Float16)sr16_round(f - weight<Q, float>(slot) * fref, rf);
+    w.y = (_Float16)sr16_round(h - weight<Q, float>(slot) * href, rh);
+  } else {
+    w.x = (_Float16)(f - weight<Q, float>(slot) * fref);
+    w.y = (_Float16)(h - weight<Q, float>(slot) * href);
+  }
   __builtin_nontemporal_store(w, reinterpret_cast<__attribute__((address_space(1))) hpair *>(p + pair_byte_off<Q, W64>((uint32_t)m)));
 }
 
@@ -292,6 +322,8 @@ __device__ __forceinline__ typename StT<ST>::R roundtrip(int i, typename StT<ST>
   using R = typename T::R;
   if constexpr (ST == ST_FP32_SR) {
     return R(sr_round(v, sr));
+  } else if constexpr (ST == ST_FP16_SR) {
+    return sr16_round(v - weight<Q, R>(i) * ref, sr) + weight<Q, R>(i) * ref;
   } else if constexpr (!T::DEV) {
     return v;
   } else {
@@ -537,9 +569,10 @@ __device__ __forceinline__ void xr_put(int lat, int i, R v) {
   xr_lds<R>()[(lat * xr_dirs<Q>() + xr_index<Q>(i)) * 256 + threadIdx.x] = v;
 }
 
-template <int Q, bool W64>
+template <int Q, int ST, bool W64>
 __device__ __forceinline__ void xr_pair_stores(const KArgs &a, const Node &c, const float *lds, int sp, int sm,
-                                               uint32_t xp, uint32_t xm) {
+                                               uint32_t xp, uint32_t xm, uint32_t src) {
+  constexpr bool SR = sr_st(ST);
 #pragma unroll
   for (int k = 0; k < Q; k++) {
     const int i = dir_at_pos<Q>(k);
@@ -547,8 +580,11 @@ __device__ __forceinline__ void xr_pair_stores(const KArgs &a, const Node &c, co
     const int s = Lat<Q>::ex(i) > 0 ? sp : sm;
     uint32_t node = (Lat<Q>::ex(i) > 0 ? xp : xm) + c.Y[1 + Lat<Q>::ey(i)];
     if constexpr (Lat<Q>::D == 3) node += c.Z[1 + Lat<Q>::ez(i)];
-    stp_pair<Q, W64>(a.fdst, i, (int64_t)node, lds[xr_index<Q>(i) * 256 + s],
-                     lds[(xr_dirs<Q>() + xr_index<Q>(i)) * 256 + s], float(a.fref), float(a.href));
+    // FP16_SR: the draws of the value's node and direction
+    const uint32_t r = SR ? sr_hash(src + (uint32_t)s, a.sr_seed) : 0u;
+    stp_pair<Q, W64, SR>(a.fdst, i, (int64_t)node, lds[xr_index<Q>(i) * 256 + s],
+                         lds[(xr_dirs<Q>() + xr_index<Q>(i)) * 256 + s], float(a.fref), float(a.href),
+                         r + (uint32_t)i * SR_WEYL, r + (uint32_t)(Q + i) * SR_WEYL);
   }
 }
 
@@ -567,12 +603,16 @@ __device__ __forceinline__ void xr_store(const KArgs &a, const Node &c) {
   uint32_t xp = x0 + (uint32_t)sp + 1u;
   if (xp >= nx) xp -= nx;
   const uint32_t xm = (x0 + (uint32_t)sm == 0u) ? nx - 1u : x0 + (uint32_t)sm - 1u;
-  if constexpr (NS && ST == ST_FP16_DEV) {
+  // node of source thread s: src + s (FP16_SR draws follow the value's node,
+  // as in the other layouts)
+  uint32_t src = x0 + c.Y[1];
+  if constexpr (Lat<Q>::D == 3) src += c.Z[1];
+  if constexpr (NS && half_st(ST)) {
     // FP16 pairs: f and h of a slot in one store
     if (a.pair64)
-      xr_pair_stores<Q, true>(a, c, lds, sp, sm, xp, xm);
+      xr_pair_stores<Q, ST, true>(a, c, lds, sp, sm, xp, xm, src);
     else
-      xr_pair_stores<Q, false>(a, c, lds, sp, sm, xp, xm);
+      xr_pair_stores<Q, ST, false>(a, c, lds, sp, sm, xp, xm, src);
     return;
   }
 #pragma unroll
@@ -585,7 +625,10 @@ __device__ __forceinline__ void xr_store(const KArgs &a, const Node &c) {
       const R v = lds[(lat * xr_dirs<Q>() + xr_index<Q>(i)) * 256 + (plus ? sp : sm)];
       uint32_t node = (plus ? xp : xm) + c.Y[1 + Lat<Q>::ey(i)];
       if constexpr (Lat<Q>::D == 3) node += c.Z[1 + Lat<Q>::ez(i)];
-      stp<Q, ST, NS ? 2 : 1>(lat ? a.hdst : a.fdst, i, a.ps, (int64_t)node, v, R(lat ? a.href : a.fref));
+      stp<Q, ST, NS ? 2 : 1>(lat ? a.hdst : a.fdst, i, a.ps, (int64_t)node, v, R(lat ? a.href : a.fref),
+                             sr_st(ST) ? sr_hash(src + (uint32_t)(plus ? sp : sm), a.sr_seed) +
+                                             (uint32_t)(lat ? Q + i : i) * SR_WEYL
+                                       : 0u);
     }
   }
 }
@@ -603,8 +646,10 @@ __device__ __forceinline__ void pair_loads(const KArgs &a, const Node &c, int64_
     ldp_pair<Q, W64>(a.fsrc, sl, nd, float(a.fref), float(a.href), f[i], h[i]);
   }
 }
-template <int Q, int LAY, bool XR, bool W64>
+template <int Q, int ST, int LAY, bool XR, bool W64>
 __device__ __forceinline__ void pair_stores(const KArgs &a, const Node &c, int64_t m, const float *f, const float *h) {
+  constexpr bool SR = sr_st(ST);
+  const uint32_t r = SR ? sr_hash((uint32_t)m, a.sr_seed) : 0u;
 #pragma unroll
   for (int k = 0; k < Q; k++) {
     const int i = dir_at_pos<Q>(k);
@@ -612,7 +657,8 @@ __device__ __forceinline__ void pair_stores(const KArgs &a, const Node &c, int64
     int sl;
     int64_t nd;
     store_addr<Q, LAY>(a, c, m, i, sl, nd);
-    stp_pair<Q, W64>(a.fdst, sl, nd, f[i], h[i], float(a.fref), float(a.href));
+    stp_pair<Q, W64, SR>(a.fdst, sl, nd, f[i], h[i], float(a.fref), float(a.href), r + (uint32_t)i * SR_WEYL,
+                         r + (uint32_t)(Q + i) * SR_WEYL);
   }
 }
 
@@ -633,7 +679,7 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
                                             typename StT<ST>::R *h) {
   using R = typename StT<ST>::R;
   constexpr int D = Lat<Q>::D;
-  constexpr bool PR = NS && ST == ST_FP16_DEV;
+  constexpr bool PR = NS && half_st(ST);
   // a central-moment f step takes rho and u from its own transform
   constexpr bool OWN_U = NS && MODE == MODE_STEP && !(CU & 2);
   R rho = 0, ux = 0, uy = 0, uz = 0;
@@ -642,7 +688,7 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
   else if constexpr (!NS)
     prescribed_u<Q, R>(a, m, ux, uy, uz);
   const R src = a.src ? static_cast<const R *>(a.src)[m] : R(0);
-  const uint32_t sr = ST == ST_FP32_SR ? sr_hash((uint32_t)m, a.sr_seed) : 0u;
+  const uint32_t sr = sr_st(ST) ? sr_hash((uint32_t)m, a.sr_seed) : 0u;
   if constexpr (MODE == MODE_STEP) {
     R g[Q];
     if constexpr (NS) {
@@ -699,9 +745,9 @@ __device__ __forceinline__ void finish_node(const KArgs &a, Node c, int64_t m, t
     }
     if constexpr (PR) {
       if (a.pair64)
-        pair_stores<Q, LAY, XR, true>(a, c, m, f, h);
+        pair_stores<Q, ST, LAY, XR, true>(a, c, m, f, h);
       else
-        pair_stores<Q, LAY, XR, false>(a, c, m, f, h);
+        pair_stores<Q, ST, LAY, XR, false>(a, c, m, f, h);
     }
     if constexpr (XR) {
       static_assert(LAY == LAY_AA_S, "realigned pushes belong to the swapped in-place phase");
@@ -827,7 +873,7 @@ __device__ __forceinline__ void bulk_node(const KArgs &a, int64_t m) {
   if constexpr (GEOM) cl = a.cls[m];
   const Node c = coords<Q>(a, m);
   R f[Q], h[Q];
-  if constexpr (NS && ST == ST_FP16_DEV) {
+  if constexpr (NS && half_st(ST)) {
     if (a.pair64)
       pair_loads<Q, LAY, true>(a, c, m, f, h);
     else
@@ -1062,13 +1108,13 @@ __device__ __forceinline__ void special_node(const KArgs &a, int64_t t) {
         finish_node<Q, ST, NS, MODE, LAY, CU>(a, coords<Q>(a, up), up, fu, hu);
         if constexpr (MODE == MODE_STEP)
           save_side<Q, ST, NS>(a, sp.ub, sp.umask, 2 * t + 1, fu, hu,
-                               ST == ST_FP32_SR ? sr_hash((uint32_t)up, a.sr_seed) : 0u);
+                               sr_st(ST) ? sr_hash((uint32_t)up, a.sr_seed) : 0u);
       }
     }
   }
   finish_node<Q, ST, NS, MODE, LAY, CU>(a, c, m, f, h);
   if constexpr (AA && MODE == MODE_STEP)
-    save_side<Q, ST, NS>(a, sp.lb, sp.mask, 2 * t, f, h, ST == ST_FP32_SR ? sr_hash((uint32_t)m, a.sr_seed) : 0u);
+    save_side<Q, ST, NS>(a, sp.lb, sp.mask, 2 * t, f, h, sr_st(ST) ? sr_hash((uint32_t)m, a.sr_seed) : 0u);
 }
 
 template <int Q, int ST, bool NS, int MODE, int LAY, int CU = 0>
@@ -1158,7 +1204,7 @@ __global__ void __launch_bounds__(256) k_init(const InitArgs a) {
     }
     if (Lat<Q>::D == 2) uz = 0.0;
     const int slot = LAY == LAY_AB ? i : Lat<Q>::opp(i);
-    const uint32_t sr = ST == ST_FP32_SR ? sr_hash((uint32_t)m, 0u) : 0u;
+    const uint32_t sr = sr_st(ST) ? sr_hash((uint32_t)m, 0u) : 0u;
     if constexpr (NS) {
       const double rho = a.rho ? a.rho[s] : 1.0;
       stp<Q, ST, NS ? 2 : 1>(a.fdst, slot, a.ps, m, R(geq_dir<Q, double>(i, rho, ux, uy, uz)), R(a.fref),
@@ -1179,7 +1225,7 @@ __global__ void __launch_bounds__(256) k_convert(const KArgs a, const void *from
   if (m >= a.n) return;
   const Node c = coords<Q>(a, m);
   const bool solid = a.cls && a.cls[m] == CLS_SOLID;
-  const uint32_t sr = ST == ST_FP32_SR ? sr_hash((uint32_t)m, a.sr_seed) : 0u;
+  const uint32_t sr = sr_st(ST) ? sr_hash((uint32_t)m, a.sr_seed) : 0u;
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     int sl;

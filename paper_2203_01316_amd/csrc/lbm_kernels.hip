@@ -25,6 +25,8 @@ LBM_DECLARE(q27_fp32dev)
 LBM_DECLARE(q27_fp16dev)
 LBM_DECLARE(q9_fp32sr)
 LBM_DECLARE(q27_fp32sr)
+LBM_DECLARE(q9_fp16sr)
+LBM_DECLARE(q27_fp16sr)
 
 // (lattice, storage) -> the launcher of that translation unit
 #define LBM_SELECT(Q, ST, F, ...)                                              \
@@ -36,6 +38,7 @@ LBM_DECLARE(q27_fp32sr)
         case ST_FP32_DEV: return q9_fp32dev_##F(__VA_ARGS__);                  \
         case ST_FP16_DEV: return q9_fp16dev_##F(__VA_ARGS__);                  \
         case ST_FP32_SR: return q9_fp32sr_##F(__VA_ARGS__);                    \
+        case ST_FP16_SR: return q9_fp16sr_##F(__VA_ARGS__);                    \
       }                                                                        \
     } else if (Q == 27) {                                                      \
       switch (ST) {                                                            \
@@ -44,6 +47,7 @@ LBM_DECLARE(q27_fp32sr)
         case ST_FP32_DEV: return q27_fp32dev_##F(__VA_ARGS__);                 \
         case ST_FP16_DEV: return q27_fp16dev_##F(__VA_ARGS__);                 \
         case ST_FP32_SR: return q27_fp32sr_##F(__VA_ARGS__);                   \
+        case ST_FP16_SR: return q27_fp16sr_##F(__VA_ARGS__);                   \
       }                                                                        \
     }                                                                          \
     return hipErrorInvalidValue;                                               \

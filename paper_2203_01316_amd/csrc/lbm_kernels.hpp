@@ -140,7 +140,7 @@ struct InitArgs {
 };
 
 // storage codes (lbm_storage)
-enum : int { ST_FP64 = 0, ST_FP32 = 1, ST_FP32_DEV = 2, ST_FP16_DEV = 3, ST_FP32_SR = 4 };
+enum : int { ST_FP64 = 0, ST_FP32 = 1, ST_FP32_DEV = 2, ST_FP16_DEV = 3, ST_FP32_SR = 4, ST_FP16_SR = 5 };
 
 // Launchers; return hipSuccess or the launch error.  lay: LAY_*.  cu: the
 // collision of each lattice in MODE_STEP (bit 0 h, bit 1 f: cumulants, else

@@ -1,0 +1,7 @@
+// Kernels of lbm_impl.hpp for D2Q9 with fp16sr storage (one translation unit
+// per lattice and storage, so the build compiles them in parallel).
+#include "lbm_impl.hpp"
+
+namespace lbm {
+LBM_INSTANTIATE(9, ST_FP16_SR, q9_fp16sr)
+}  // namespace lbm

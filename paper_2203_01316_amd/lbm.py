@@ -26,7 +26,7 @@ _lib = C.CDLL(LIB_PATH)
 # enums (include/lbm.h)
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED, EDIVERGED = 0, -1, -2, -3, -4, -5, -6
 D2Q9, D3Q27 = 9, 27
-FP64, FP32, FP32_DEV, FP16_DEV, FP32_SR = 0, 1, 2, 3, 4
+FP64, FP32, FP32_DEV, FP16_DEV, FP32_SR, FP16_SR = 0, 1, 2, 3, 4, 5
 STREAM_AB, STREAM_AA = 0, 1
 CM_SRT, CM_1ST, CM_TRT, CM_NS, CM_CUSTOM = 0, 1, 2, 3, 4
 FLUID, SOLID, EQ, OUTLET = 0, 1, 2, 3
@@ -35,7 +35,8 @@ ABB, IABB = 0, 1
 _STATUS = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE",
            EUNSUPPORTED: "EUNSUPPORTED", EDIVERGED: "EDIVERGED"}
 _RELAX = {"srt": CM_SRT, "1st": CM_1ST, "trt": CM_TRT, "ns": CM_NS, "custom": CM_CUSTOM}
-_STORAGE = {"fp64": FP64, "fp32": FP32, "fp32_dev": FP32_DEV, "fp16_dev": FP16_DEV, "fp32_sr": FP32_SR}
+_STORAGE = {"fp64": FP64, "fp32": FP32, "fp32_dev": FP32_DEV, "fp16_dev": FP16_DEV, "fp32_sr": FP32_SR,
+            "fp16_sr": FP16_SR}
 
 
 class Params(C.Structure):

@@ -257,7 +257,7 @@ def _random_state(n, D, seed):
     return u, 1 + 1e-3 * rng.standard_normal(n), 10 + rng.standard_normal(n)
 
 
-@pytest.mark.parametrize("storage", ["fp32", "fp32_dev", "fp16_dev"])
+@pytest.mark.parametrize("storage", ["fp32", "fp32_dev", "fp16_dev", "fp16_sr"])
 @pytest.mark.parametrize("case", ["d2q9_one_block_rows", "d2q9_two_block_rows", "d2q9_ade_two_block_rows",
                                   "d3q27_one_block_rows", "d3q27_cumulant"])
 def test_aa_realigned_pushes(L, case, storage):
@@ -295,7 +295,7 @@ def test_aa_realigned_pushes(L, case, storage):
         _same(L, ab, aa, ("f", "h") if ns else ("h",))
 
 
-@pytest.mark.parametrize("storage", ["fp32", "fp32_dev", "fp16_dev"])
+@pytest.mark.parametrize("storage", ["fp32", "fp32_dev", "fp16_dev", "fp16_sr"])
 @pytest.mark.parametrize("nx", [256, 512])
 def test_aa_rows_of_whole_blocks_with_geometry(L, nx, storage):
     """Rows of one and two whole blocks with geometry (heated cylinder with
@@ -318,7 +318,7 @@ def test_aa_rows_of_whole_blocks_with_geometry(L, nx, storage):
     for k in (1, 2, 7):
         ab.step(k)
         aa.step(k)
-        _same(L, ab, aa, ("f", "h"), exact=storage != "fp16_dev", cols=(3, nx - 20), group=1)
+        _same(L, ab, aa, ("f", "h"), exact=storage not in ("fp16_dev", "fp16_sr"), cols=(3, nx - 20), group=1)
 
 
 def test_aa_rows_of_whole_blocks_d3q27_sphere(L):

@@ -106,7 +106,7 @@ def test_c2_channel_20000_steps(L, stream, storage, tol, tol_node):
 # Config 3 parity window: 2048^2 coupled heated cylinder, 200 steps
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("storage,tol,tol_node", [("fp32", TOL32, 1e-4), ("fp16_dev", 2e-4, 2e-3),
-                                                  ("fp32_sr", TOL32, 1e-4)])
+                                                  ("fp32_sr", TOL32, 1e-4), ("fp16_sr", 2e-4, 2e-3)])
 @pytest.mark.parametrize("stream", ["ab", "aa"])
 def test_c3_cylinder_200_steps(L, storage, tol, tol_node, stream):
     """FP32 (plain, or FP64 arithmetic with stochastic rounding) within 1e-5;
@@ -153,7 +153,8 @@ def _tgv(L, n1, storage, stream, cu):
 
 @pytest.mark.parametrize("name,n1,cu", [("c4_tgv_64_t200", 64, False), ("c4_tgv_64_cu_t200", 64, True),
                                         ("c4_tgv_256_t10", 256, False)])
-@pytest.mark.parametrize("storage,tol", [("fp32", TOL32), ("fp16_dev", 2e-4), ("fp32_sr", TOL32)])
+@pytest.mark.parametrize("storage,tol", [("fp32", TOL32), ("fp16_dev", 2e-4), ("fp32_sr", TOL32),
+                                         ("fp16_sr", 2e-4)])
 @pytest.mark.parametrize("stream", ["ab", "aa"])
 def test_c4_taylor_green(L, name, n1, cu, storage, tol, stream):
     """FP32 (plain, or FP64 arithmetic with stochastic rounding) within 1e-5
