@@ -109,16 +109,29 @@ __device__ __forceinline__ float sr_round(double v, uint32_t r) {
   b &= ~((1ull << 29) - 1ull);
   return static_cast<float>(__longlong_as_double(static_cast<long long>(b)));
 }
-// FP16_SR: an FP32 deviation rounded stochastically to FP16, returned as the
-// FP32 value of that FP16 number (so the conversion that follows is exact).
-// In the normal FP16 range (|d| >= 2^-14) 13 bits of the draw go to the 13
-// mantissa bits that FP16 drops, as for FP32_SR; below it FP16 holds the
-// multiples of 2^-24, and d 2^24 plus a uniform fraction is rounded down.
-__device__ __forceinline__ float sr16_round(float d, uint32_t r) {
+// FP16_SR: an FP32 deviation d rounded stochastically to FP16.  The FP16
+// spacing at |d| is q = 2^(e - 10) for |d| >= 2^-14 (e: the exponent of d)
+// and q = 2^-24 below, among the FP16 subnormals.  A uniform draw in [0, q)
+// in steps of q / 2^13 (13 bits of r as the top mantissa bits of a number in
+// [q, 2q), minus q) is added to |d| and the sum is truncated toward zero onto
+// the FP16 numbers, which rounds |d| up with probability equal to its
+// distance above the lower neighbour in units of q.  The steps are FP32's
+// spacing at |d| in the normal FP16 range, so the sum is exact there, and an
+// FP16 value d never moves.  sr16_noised returns d with the draw added; the
+// truncation is the round-toward-zero conversion (two values per
+// instruction).
+typedef __fp16 fp16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float sr16_noised(float d, uint32_t r) {
   const uint32_t b = __float_as_uint(d);
-  if ((b & 0x7fffffffu) >= 0x38800000u) return __uint_as_float((b + (r >> 19)) & ~0x1fffu);
-  const float q = floorf(fabsf(d) * 0x1p24f + static_cast<float>(r >> 8) * 0x1p-24f);
-  return copysignf(q * 0x1p-24f, d);
+  const uint32_t qb = max(b & 0x7f800000u, 0x38800000u) - (10u << 23);
+  const float noise = __uint_as_float(qb | ((r >> 19) << 10)) - __uint_as_float(qb);
+  return d + copysignf(noise, d);
+}
+// The FP16 value of one rounding, as FP32 (so a conversion that follows is
+// exact).
+__device__ __forceinline__ float sr16_round(float d, uint32_t r) {
+  const fp16x2 p = __builtin_amdgcn_cvt_pkrtz(sr16_noised(d, r), 0.0f);
+  return static_cast<float>(p.x);
 }
 
 // Population storage.  FP64 and FP32 elements: tiles of
@@ -305,8 +318,9 @@ __device__ __forceinline__ void stp_pair(void *fbase, int slot, int64_t m, float
   const global_ptr<char> p = uniform_base(const_cast<char *>(pair_slot_base<Q>(fbase, slot)));
   hpair w;
   if constexpr (SR) {
-    w.x = (_Float16)sr16_round(f - weight<Q, float>(slot) * fref, rf);
-    w.y = (_Float16)sr16_round(h - weight<Q, float>(slot) * href, rh);
+    const fp16x2 v = __builtin_amdgcn_cvt_pkrtz(sr16_noised(f - weight<Q, float>(slot) * fref, rf),
+                                                sr16_noised(h - weight<Q, float>(slot) * href, rh));
+    w = __builtin_bit_cast(hpair, v);
   } else {
     w.x = (_Float16)(f - weight<Q, float>(slot) * fref);
     w.y = (_Float16)(h - weight<Q, float>(slot) * href);
