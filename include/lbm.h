@@ -286,7 +286,9 @@ lbm_status lbm_macroscopic(lbm_ctx *ctx, double *rho_dev, double *u_dev, double 
 lbm_status lbm_get_populations(lbm_ctx *ctx, int32_t lattice, int32_t which, double *dst_dev);
 
 /* Replaces the stored post-collision state (which = 1 layout) of one lattice
- * from a device FP64 array [Q][n] and sets the time to t. */
+ * from a device FP64 array [Q][n] and sets the time to t.  With
+ * LBM_FP32_SR or LBM_FP16_SR storage the values are rounded stochastically
+ * with the draws of time t (the same t gives the same stored state). */
 lbm_status lbm_set_populations(lbm_ctx *ctx, int32_t lattice, const double *src_dev, int64_t t);
 
 /* FP64 reductions of the canonical state at the current time (synchronises):
