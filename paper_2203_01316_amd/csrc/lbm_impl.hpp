@@ -112,8 +112,8 @@ __device__ __forceinline__ float sr_round(double v, uint32_t r) {
 // FP16_SR: an FP32 deviation d rounded stochastically to FP16.  The FP16
 // spacing at |d| is q = 2^(e - 10) for |d| >= 2^-14 (e: the exponent of d)
 // and q = 2^-24 below, among the FP16 subnormals.  A uniform draw in [0, q)
-// in steps of q / 2^13 (13 bits of r as the top mantissa bits of a number in
-// [q, 2q), minus q) is added to |d| and the sum is truncated toward zero onto
+// in steps of q / 2^13 (bits 10-22 of r as the top mantissa bits of a number
+// in [q, 2q), minus q) is added to |d| and the sum is truncated toward zero onto
 // the FP16 numbers, which rounds |d| up with probability equal to its
 // distance above the lower neighbour in units of q.  The steps are FP32's
 // spacing at |d| in the normal FP16 range, so the sum is exact there, and an
@@ -124,7 +124,7 @@ typedef __fp16 fp16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float sr16_noised(float d, uint32_t r) {
   const uint32_t b = __float_as_uint(d);
   const uint32_t qb = max(b & 0x7f800000u, 0x38800000u) - (10u << 23);
-  const float noise = __uint_as_float(qb | ((r >> 19) << 10)) - __uint_as_float(qb);
+  const float noise = __uint_as_float(qb | (r & 0x007ffc00u)) - __uint_as_float(qb);
   return d + copysignf(noise, d);
 }
 // The FP16 value of one rounding, as FP32 (so a conversion that follows is
